@@ -1,0 +1,855 @@
+/*
+ * gm_oracle.c -- plain serial FP64 oracle for adaptive Genz-Malik cubature.
+ *
+ * TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU baseline of the
+ * benchmark).  Shares no code with the HIP library.
+ *
+ * Paper: Tonarelli, Riva, Benedusi, Ferrandi, Krause, "Adaptive
+ * Multidimensional Quadrature on Multi-GPU Systems", arXiv 2511.01573.
+ * The paper names the rule (Sec. 2: a fully symmetric Genz-Malik rule with
+ * O(2^d) nodes), the error estimator family (Sec. 2: the Genz-Berntsen style
+ * heuristic built on the embedded rule), the split heuristic (Sec. 2: fourth
+ * derivative along each axis), the breadth-first loop (Sec. 3) and the
+ * stopping rule (Sec. 4).  It prints no constants; the ones below are the
+ * unique solution of the moment equations of a degree-7 fully symmetric rule
+ * with generators {0, l2 e_i, l3 e_i, l4(e_i+e_j), l5 (1,..,1)} and the
+ * degree-5 rule embedded in the same nodes.  Where the paper is silent the
+ * readings are stated at each function.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -lm
+ */
+#include "gm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Compensated (Neumaier) summation.                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double s, c;
+} ksum;
+
+static void ks_add(ksum* k, double x) {
+  double t = k->s + x;
+  if (fabs(k->s) >= fabs(x))
+    k->c += (k->s - t) + x;
+  else
+    k->c += (x - t) + k->s;
+  k->s = t;
+}
+static double ks_val(const ksum* k) { return k->s + k->c; }
+
+/* ------------------------------------------------------------------------ */
+/* Rule constants (Sec. 2, the Genz-Malik degree-7 rule and its embedded     */
+/* degree-5 rule, mean measure on [-1,1]^d).  Each value is one correctly    */
+/* rounded division of exact integers, or a square root of one.              */
+/* ------------------------------------------------------------------------ */
+int64_t gmo_num_nodes(int d) {
+  return ((int64_t)1 << d) + 2 * (int64_t)d * d + 2 * (int64_t)d + 1;
+}
+
+void gmo_constants(int d, double lam[5], double w[5], double v[5], double e[5]) {
+  int64_t D = d;
+  lam[0] = 0.0;
+  lam[1] = sqrt(9.0 / 70.0);
+  lam[2] = sqrt(9.0 / 10.0);
+  lam[3] = sqrt(9.0 / 10.0);
+  lam[4] = sqrt(9.0 / 19.0);
+  w[0] = (double)(400 * D * D - 9120 * D + 12824) / 19683.0;
+  w[1] = 980.0 / 6561.0;
+  w[2] = (double)(1820 - 400 * D) / 19683.0;
+  w[3] = 200.0 / 19683.0;
+  w[4] = ldexp(6859.0 / 19683.0, -d);
+  v[0] = (double)(50 * D * D - 950 * D + 729) / 729.0;
+  v[1] = 245.0 / 486.0;
+  v[2] = (double)(265 - 100 * D) / 1458.0;
+  v[3] = 25.0 / 729.0;
+  v[4] = 0.0;
+  /* e = w - v as exact rationals, then rounded once. */
+  e[0] = (double)(-19 * (50 * D * D - 870 * D + 361)) / 19683.0;
+  e[1] = -4655.0 / 13122.0;
+  e[2] = (double)(95 * (20 * D - 37)) / 39366.0;
+  e[3] = -475.0 / 19683.0;
+  e[4] = w[4];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integrands (Sec. 4 test functions and their seeded Genz families).        */
+/* params = a[0..d), u[0..d).  Sums run left to right over j = 0..d-1.       */
+/* ------------------------------------------------------------------------ */
+static const double TWO_PI = 6.283185307179586476925286766559;
+
+double gmo_f(int fam, int d, const double* p, const double* x) {
+  const double* a = p;
+  const double* u = p + d;
+  double s = 0.0;
+  int j;
+  switch (fam) {
+    case GMO_OSCILLATORY: /* cos(2 pi u_1 + sum a_j x_j); f1 has a_j = j, u = 0 */
+      for (j = 0; j < d; ++j) s = s + a[j] * x[j];
+      return cos(TWO_PI * u[0] + s);
+    case GMO_PRODUCT_PEAK: { /* prod 1/(a_j^-2 + (x_j-u_j)^2); f2 has a = 50, u = 1/2 */
+      double den = 1.0;
+      for (j = 0; j < d; ++j) {
+        double t = x[j] - u[j];
+        den = den * (1.0 / (a[j] * a[j]) + t * t);
+      }
+      return 1.0 / den;
+    }
+    case GMO_CORNER_PEAK: /* (1 + sum a_j x_j)^-(d+1); f3 has a_j = j */
+      for (j = 0; j < d; ++j) s = s + a[j] * x[j];
+      return pow(1.0 + s, -(double)(d + 1));
+    case GMO_GAUSSIAN: /* exp(-sum a_j^2 (x_j-u_j)^2); f4 has a = 25, u = 1/2 */
+      for (j = 0; j < d; ++j) {
+        double t = a[j] * (x[j] - u[j]);
+        s = s + t * t;
+      }
+      return exp(-s);
+    case GMO_C0: /* exp(-sum a_j |x_j-u_j|); f5 has a = 10, u = 1/2 */
+      for (j = 0; j < d; ++j) s = s + a[j] * fabs(x[j] - u[j]);
+      return exp(-s);
+    case GMO_DISCONTINUOUS: /* 0 if x_j > u_j for any j, else exp(sum a_j x_j) */
+      for (j = 0; j < d; ++j)
+        if (x[j] > u[j]) return 0.0;
+      for (j = 0; j < d; ++j) s = s + a[j] * x[j];
+      return exp(s);
+    case GMO_POLY: /* f7 = (sum x_j^2)^11 */
+      for (j = 0; j < d; ++j) s = s + x[j] * x[j];
+      return pow(s, 11.0);
+    case GMO_MONOMIAL: { /* test family: prod (x_j - u_j)^k_j, k_j = (int)a_j */
+      double m = 1.0;
+      for (j = 0; j < d; ++j) {
+        int k, kj = (int)a[j];
+        double t = x[j] - u[j];
+        for (k = 0; k < kj; ++k) m = m * t;
+      }
+      return m;
+    }
+    default:
+      return NAN;
+  }
+}
+
+/* Partial derivatives of f with respect to a_j (out[j]) and u_j (out[d+j]).
+   The discontinuous family's jump location does not enter the fixed-tree
+   quadrature (nodes do not move), so its u-derivatives are zero. */
+double gmo_df(int fam, int d, const double* p, const double* x, double* out) {
+  const double* a = p;
+  const double* u = p + d;
+  double f = gmo_f(fam, d, p, x);
+  int j;
+  for (j = 0; j < 2 * d; ++j) out[j] = 0.0;
+  switch (fam) {
+    case GMO_OSCILLATORY: {
+      double s = 0.0;
+      for (j = 0; j < d; ++j) s = s + a[j] * x[j];
+      double sn = sin(TWO_PI * u[0] + s);
+      for (j = 0; j < d; ++j) out[j] = -sn * x[j];
+      out[d] = -sn * TWO_PI;
+      break;
+    }
+    case GMO_PRODUCT_PEAK:
+      for (j = 0; j < d; ++j) {
+        double t = x[j] - u[j];
+        double den = 1.0 / (a[j] * a[j]) + t * t;
+        out[j] = 2.0 * f / (a[j] * a[j] * a[j] * den);
+        out[d + j] = 2.0 * f * t / den;
+      }
+      break;
+    case GMO_CORNER_PEAK: {
+      double s = 0.0;
+      for (j = 0; j < d; ++j) s = s + a[j] * x[j];
+      double g = -(double)(d + 1) * f / (1.0 + s);
+      for (j = 0; j < d; ++j) out[j] = g * x[j];
+      break;
+    }
+    case GMO_GAUSSIAN:
+      for (j = 0; j < d; ++j) {
+        double t = x[j] - u[j];
+        out[j] = -2.0 * a[j] * t * t * f;
+        out[d + j] = 2.0 * a[j] * a[j] * t * f;
+      }
+      break;
+    case GMO_C0:
+      for (j = 0; j < d; ++j) {
+        double t = x[j] - u[j];
+        out[j] = -fabs(t) * f;
+        out[d + j] = (t > 0.0 ? 1.0 : (t < 0.0 ? -1.0 : 0.0)) * a[j] * f;
+      }
+      break;
+    case GMO_DISCONTINUOUS:
+      for (j = 0; j < d; ++j) out[j] = x[j] * f;
+      break;
+    default:
+      break;
+  }
+  return f;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Node generation (Sec. 2: fully symmetric rule).  x = c + h*g with        */
+/* generators, in this visit order:                                          */
+/*   class 1: the centre;                                                    */
+/*   class 2: +l2 e_i, -l2 e_i for i = 0..d-1;                                */
+/*   class 3: +l3 e_i, -l3 e_i;                                               */
+/*   class 4: for i < j: (+,+), (+,-), (-,+), (-,-) times l4 on (i, j);       */
+/*   class 5: b = 0..2^d-1, coordinate j takes -l5 when bit j of b is set.    */
+/* Each perturbed coordinate is fma(sigma*lambda, h_j, c_j).                 */
+/* ------------------------------------------------------------------------ */
+typedef void (*node_visitor)(void* ctx, int cls, const double* x);
+
+static void visit_nodes(int d, const double* c, const double* h, node_visitor fn, void* ctx) {
+  double lam[5], w[5], v[5], e[5];
+  double x[64];
+  int i, j, k;
+  gmo_constants(d, lam, w, v, e);
+  for (k = 0; k < d; ++k) x[k] = c[k];
+  fn(ctx, 1, x);
+  for (k = 2; k <= 3; ++k) {
+    double l = lam[k - 1];
+    for (i = 0; i < d; ++i) {
+      x[i] = fma(l, h[i], c[i]);
+      fn(ctx, k, x);
+      x[i] = fma(-l, h[i], c[i]);
+      fn(ctx, k, x);
+      x[i] = c[i];
+    }
+  }
+  {
+    double l = lam[3];
+    for (i = 0; i < d; ++i)
+      for (j = i + 1; j < d; ++j) {
+        int si, sj;
+        for (si = 0; si < 2; ++si)
+          for (sj = 0; sj < 2; ++sj) {
+            x[i] = fma(si ? -l : l, h[i], c[i]);
+            x[j] = fma(sj ? -l : l, h[j], c[j]);
+            fn(ctx, 4, x);
+          }
+        x[i] = c[i];
+        x[j] = c[j];
+      }
+  }
+  {
+    double l = lam[4];
+    int64_t b, nb = (int64_t)1 << d;
+    for (b = 0; b < nb; ++b) {
+      for (k = 0; k < d; ++k) x[k] = fma(((b >> k) & 1) ? -l : l, h[k], c[k]);
+      fn(ctx, 5, x);
+    }
+  }
+}
+
+typedef struct {
+  int d;
+  int64_t n;
+  double* x;
+  int* cls;
+} nodes_ctx;
+
+static void nodes_cb(void* p, int cls, const double* x) {
+  nodes_ctx* q = (nodes_ctx*)p;
+  memcpy(q->x + q->n * q->d, x, sizeof(double) * q->d);
+  q->cls[q->n] = cls;
+  q->n++;
+}
+
+void gmo_nodes(int d, const double* c, const double* h, double* x, int* cls) {
+  nodes_ctx q = {d, 0, x, cls};
+  visit_nodes(d, c, h, nodes_cb, &q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* One region: rule value, error estimate, split axis (Sec. 2).             */
+/*                                                                          */
+/* Q   = vol * sum_k w_k S_k                       (degree-7 rule)          */
+/* err = vol * |sum_k (w_k - v_k) S_k| = |Q7 - Q5| (embedded-rule estimate) */
+/* D_i = |A_i - B_i/7|, A_i = f(c+l2 h_i e_i) + f(c-l2 h_i e_i) - 2 f(c),   */
+/*       B_i the same with l3; 1/7 = l2^2/l3^2 cancels the second           */
+/*       derivative, leaving a fourth-difference estimate.                   */
+/* Split axis (reading; the paper only says "largest estimate"): every D_i  */
+/* within a noise band of the largest is a candidate, band = 1e-10 times    */
+/* the largest sum of the magnitudes that enter one D_i; among candidates   */
+/* the widest h_i wins, then the lowest index.                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int fam, d;
+  const double* p;
+  ksum S[5];
+  double Sabs[5];
+  double f0;
+  double f2[32], f3[32]; /* [2i] = +, [2i+1] = - */
+  int n2, n3;
+  int nonfinite;
+} rule_ctx;
+
+static void rule_cb(void* pp, int cls, const double* x) {
+  rule_ctx* r = (rule_ctx*)pp;
+  double f = gmo_f(r->fam, r->d, r->p, x);
+  if (!isfinite(f)) r->nonfinite = 1;
+  ks_add(&r->S[cls - 1], f);
+  r->Sabs[cls - 1] += fabs(f);
+  if (cls == 1) r->f0 = f;
+  if (cls == 2) r->f2[r->n2++] = f;
+  if (cls == 3) r->f3[r->n3++] = f;
+}
+
+static const double AXIS_BAND = 1e-10;
+
+int gmo_rule(int fam, int d, const double* params, const double* c, const double* h, int lvl,
+             double vol_omega, double* out) {
+  double lam[5], w[5], v[5], e[5];
+  rule_ctx r;
+  int k, i;
+  double S[5], vol, q, er, sq, se;
+  gmo_constants(d, lam, w, v, e);
+  memset(&r, 0, sizeof r);
+  r.fam = fam;
+  r.d = d;
+  r.p = params;
+  visit_nodes(d, c, h, rule_cb, &r);
+  for (k = 0; k < 5; ++k) S[k] = ks_val(&r.S[k]);
+  for (k = 0; k < 5; ++k)
+    if (!isfinite(S[k])) r.nonfinite = 1;
+  vol = ldexp(vol_omega, -lvl);
+  q = w[0] * S[0] + w[1] * S[1];
+  q = q + w[2] * S[2];
+  q = q + w[3] * S[3];
+  q = q + w[4] * S[4];
+  er = e[0] * S[0] + e[1] * S[1];
+  er = er + e[2] * S[2];
+  er = er + e[3] * S[3];
+  er = er + e[4] * S[4];
+  sq = 0.0;
+  se = 0.0;
+  for (k = 0; k < 5; ++k) {
+    sq += fabs(w[k]) * r.Sabs[k];
+    se += fabs(e[k]) * r.Sabs[k];
+  }
+  out[0] = vol * q;
+  out[1] = vol * fabs(er);
+  out[4] = vol * sq;
+  out[5] = vol * se;
+  for (k = 0; k < 5; ++k) {
+    out[6 + k] = S[k];
+    out[11 + k] = r.Sabs[k];
+  }
+  {
+    const double r7 = 1.0 / 7.0;
+    double Dmax = -1.0, scale = 0.0, band;
+    int axis = 0;
+    double D[32];
+    for (i = 0; i < d; ++i) {
+      double A = (r.f2[2 * i] + r.f2[2 * i + 1]) - 2.0 * r.f0;
+      double B = (r.f3[2 * i] + r.f3[2 * i + 1]) - 2.0 * r.f0;
+      double m = (fabs(r.f2[2 * i]) + fabs(r.f2[2 * i + 1]) + 2.0 * fabs(r.f0)) +
+                 r7 * (fabs(r.f3[2 * i]) + fabs(r.f3[2 * i + 1]) + 2.0 * fabs(r.f0));
+      D[i] = fabs(A - B * r7);
+      out[16 + i] = D[i];
+      if (D[i] > Dmax) Dmax = D[i];
+      if (m > scale) scale = m;
+    }
+    band = AXIS_BAND * scale;
+    axis = -1;
+    for (i = 0; i < d; ++i) {
+      if (D[i] >= Dmax - band) {
+        if (axis < 0 || h[i] > h[axis]) axis = i;
+      }
+    }
+    out[2] = (double)axis;
+    {
+      double hp = h[axis] * 0.5;
+      int geo = (c[axis] - hp == c[axis]) || (c[axis] + hp == c[axis]) || (hp == 0.0);
+      out[3] = geo ? 1.0 : 0.0;
+    }
+  }
+  return r.nonfinite ? GMO_NONFINITE : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive loop (Sec. 3 workflow, Sec. 4 stopping rule).                   */
+/*                                                                          */
+/* 1. Initial uniform partition: s = 2^floor(L0/d) cells per axis, cell     */
+/*    t = sum_j k_j s^j (axis 0 fastest), h_j = ldexp(H_j, -m),             */
+/*    c_j = fma(2 k_j + 1, h_j, lo_j), level m*d.                           */
+/* 2. Evaluate every active region.                                         */
+/* 3. I = I_fin + sum Q, E = E_fin + sum err (compensated, store order);     */
+/*    T = max(abs_tol, rel_tol |I|); stop when E <= T.                       */
+/* 4. Stop when the iteration budget is used up.                            */
+/* 5. Classifier (reading of "discards subregions whose contribution to     */
+/*    the error is negligible"): a region retires if                        */
+/*      (a) err <= ldexp(T, -lvl)   (its error density is within budget),    */
+/*      (b) fl(|I| + err) == |I|    (round-off guard), or                   */
+/*      (c) halving along its axis changes nothing (geometry guard).         */
+/* 6. Retired regions join I_fin, E_fin (and the leaf list).                 */
+/* 7. No region left -> precision limit; 2*n_keep > capacity -> stop.        */
+/* 8. Split each kept region in half along its axis: child "-" at rank p,   */
+/*    child "+" at n_keep + p (stable order).                               */
+/* ------------------------------------------------------------------------ */
+struct gmo_run {
+  int fam, d, max_iters, keep_leaves;
+  double params[32];
+  double rel_tol, abs_tol, vol_omega;
+  int64_t max_regions;
+  int status;
+  int iter;
+  int64_t n;   /* active count */
+  int64_t cap; /* allocated rows */
+  double *c, *h, *Q, *err;
+  int32_t *lvl, *axis;
+  unsigned char *geo, *fin;
+  double I, E, T;
+  ksum Ifin, Efin;
+  int64_t n_keep;
+  int64_t stats[8];
+  /* leaves */
+  int64_t nleaf, leafcap;
+  double *lc, *lh;
+  int32_t* llvl;
+  /* trace */
+  int64_t ntr, trcap;
+  int64_t* trc;
+  double* trv;
+};
+
+static int grow(gmo_run* r, int64_t need) {
+  int64_t nc;
+  if (need <= r->cap) return 0;
+  nc = r->cap ? r->cap : 1024;
+  while (nc < need) nc *= 2;
+  r->c = (double*)realloc(r->c, sizeof(double) * nc * r->d);
+  r->h = (double*)realloc(r->h, sizeof(double) * nc * r->d);
+  r->Q = (double*)realloc(r->Q, sizeof(double) * nc);
+  r->err = (double*)realloc(r->err, sizeof(double) * nc);
+  r->lvl = (int32_t*)realloc(r->lvl, sizeof(int32_t) * nc);
+  r->axis = (int32_t*)realloc(r->axis, sizeof(int32_t) * nc);
+  r->geo = (unsigned char*)realloc(r->geo, nc);
+  r->fin = (unsigned char*)realloc(r->fin, nc);
+  if (!r->c || !r->h || !r->Q || !r->err || !r->lvl || !r->axis || !r->geo || !r->fin) return -1;
+  r->cap = nc;
+  return 0;
+}
+
+static int leaf_push(gmo_run* r, const double* c, const double* h, int32_t lvl) {
+  int d = r->d;
+  if (r->nleaf == r->leafcap) {
+    int64_t nc = r->leafcap ? 2 * r->leafcap : 1024;
+    r->lc = (double*)realloc(r->lc, sizeof(double) * nc * d);
+    r->lh = (double*)realloc(r->lh, sizeof(double) * nc * d);
+    r->llvl = (int32_t*)realloc(r->llvl, sizeof(int32_t) * nc);
+    if (!r->lc || !r->lh || !r->llvl) return -1;
+    r->leafcap = nc;
+  }
+  memcpy(r->lc + r->nleaf * d, c, sizeof(double) * d);
+  memcpy(r->lh + r->nleaf * d, h, sizeof(double) * d);
+  r->llvl[r->nleaf] = lvl;
+  r->nleaf++;
+  return 0;
+}
+
+static void trace_push(gmo_run* r, int64_t nact, int64_t nfin) {
+  if (r->ntr == r->trcap) {
+    int64_t nc = r->trcap ? 2 * r->trcap : 64;
+    r->trc = (int64_t*)realloc(r->trc, sizeof(int64_t) * 2 * nc);
+    r->trv = (double*)realloc(r->trv, sizeof(double) * 2 * nc);
+    r->trcap = nc;
+  }
+  r->trc[2 * r->ntr] = nact;
+  r->trc[2 * r->ntr + 1] = nfin;
+  r->trv[2 * r->ntr] = r->I;
+  r->trv[2 * r->ntr + 1] = r->E;
+  r->ntr++;
+}
+
+gmo_run* gmo_create(int fam, int d, const double* params, const double* lo, const double* hi,
+                    double rel_tol, double abs_tol, int64_t max_regions, int init_log2,
+                    int max_iters, int keep_leaves, int* status) {
+  gmo_run* r;
+  int j, m;
+  int64_t s, n0, t;
+  double H[32];
+  *status = GMO_EINVAL;
+  if (d < 2 || d > 16 || ((fam < 1 || fam > 7) && fam != GMO_MONOMIAL) || init_log2 < 0 || init_log2 > 40 || max_iters < 1)
+    return NULL;
+  if (!(rel_tol >= 0.0) || !(abs_tol >= 0.0) || !isfinite(rel_tol) || !isfinite(abs_tol) ||
+      (rel_tol == 0.0 && abs_tol == 0.0))
+    return NULL;
+  for (j = 0; j < d; ++j)
+    if (!isfinite(lo[j]) || !isfinite(hi[j]) || !(lo[j] < hi[j])) return NULL;
+  for (j = 0; j < 2 * d; ++j)
+    if (!isfinite(params[j])) return NULL;
+  m = init_log2 / d;
+  s = (int64_t)1 << m;
+  n0 = (int64_t)1 << (m * d);
+  if (max_regions < n0) return NULL;
+  r = (gmo_run*)calloc(1, sizeof(gmo_run));
+  if (!r) {
+    *status = GMO_ENOMEM;
+    return NULL;
+  }
+  r->fam = fam;
+  r->d = d;
+  r->max_iters = max_iters;
+  r->keep_leaves = keep_leaves;
+  memcpy(r->params, params, sizeof(double) * 2 * d);
+  r->rel_tol = rel_tol;
+  r->abs_tol = abs_tol;
+  r->max_regions = max_regions;
+  r->vol_omega = 1.0;
+  for (j = 0; j < d; ++j) r->vol_omega = r->vol_omega * (hi[j] - lo[j]);
+  if (grow(r, n0)) {
+    gmo_free(r);
+    *status = GMO_ENOMEM;
+    return NULL;
+  }
+  for (j = 0; j < d; ++j) H[j] = (hi[j] - lo[j]) * 0.5;
+  for (t = 0; t < n0; ++t) {
+    for (j = 0; j < d; ++j) {
+      int64_t kj = (t >> (m * j)) & (s - 1);
+      double hj = ldexp(H[j], -m);
+      r->h[t * d + j] = hj;
+      r->c[t * d + j] = fma((double)(2 * kj + 1), hj, lo[j]);
+    }
+    r->lvl[t] = m * d;
+  }
+  r->n = n0;
+  r->status = GMO_RUNNING;
+  *status = GMO_RUNNING;
+  return r;
+}
+
+/* Phase A: evaluate, global test, classify (nothing committed yet). */
+static int phase_eval(gmo_run* r) {
+  int64_t i;
+  int d = r->d;
+  ksum Is = r->Ifin, Es = r->Efin;
+  double out[16 + 32];
+  r->iter++;
+  r->stats[GMO_ST_ITERS] = r->iter;
+  r->stats[GMO_ST_REGIONS] += r->n;
+  r->stats[GMO_ST_EVALS] += r->n * gmo_num_nodes(d);
+  r->stats[GMO_ST_ACTIVE] = r->n;
+  if (r->n > r->stats[GMO_ST_MAX_ACTIVE]) r->stats[GMO_ST_MAX_ACTIVE] = r->n;
+  for (i = 0; i < r->n; ++i) {
+    int rc = gmo_rule(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
+                      out);
+    if (rc == GMO_NONFINITE) {
+      r->I = NAN;
+      r->E = NAN;
+      r->status = GMO_NONFINITE;
+      trace_push(r, r->n, 0);
+      return r->status;
+    }
+    r->Q[i] = out[0];
+    r->err[i] = out[1];
+    r->axis[i] = (int32_t)out[2];
+    r->geo[i] = (unsigned char)out[3];
+  }
+  for (i = 0; i < r->n; ++i) ks_add(&Is, r->Q[i]);
+  for (i = 0; i < r->n; ++i) ks_add(&Es, r->err[i]);
+  r->I = ks_val(&Is);
+  r->E = ks_val(&Es);
+  r->T = fmax(r->abs_tol, r->rel_tol * fabs(r->I));
+  if (r->E <= r->T) {
+    r->status = GMO_OK;
+    trace_push(r, r->n, 0);
+    return r->status;
+  }
+  if (r->iter >= r->max_iters) {
+    r->status = GMO_MAX_ITERS;
+    trace_push(r, r->n, 0);
+    return r->status;
+  }
+  {
+    double aI = fabs(r->I);
+    int64_t keep = 0, nfin = 0;
+    for (i = 0; i < r->n; ++i) {
+      int a = r->err[i] <= ldexp(r->T, -r->lvl[i]);
+      int b = (aI + r->err[i] == aI);
+      int g = r->geo[i];
+      r->fin[i] = (unsigned char)(a || b || g);
+      if (r->fin[i]) nfin++;
+      else keep++;
+    }
+    r->n_keep = keep;
+    trace_push(r, r->n, nfin);
+  }
+  if (r->n_keep == 0) {
+    r->status = GMO_PRECISION_LIMIT;
+    return r->status;
+  }
+  return GMO_RUNNING;
+}
+
+/* Phase C: commit retired regions and split the kept ones. */
+static int phase_split(gmo_run* r) {
+  int d = r->d;
+  int64_t i, p = 0, nk = r->n_keep, n2 = 2 * r->n_keep;
+  double *nc_, *nh_;
+  int32_t* nl_;
+  double aI = fabs(r->I);
+  for (i = 0; i < r->n; ++i) {
+    if (r->fin[i]) {
+      ks_add(&r->Ifin, r->Q[i]);
+      ks_add(&r->Efin, r->err[i]);
+      r->stats[GMO_ST_FINISHED]++;
+      if (r->geo[i]) r->stats[GMO_ST_GEOMETRY]++;
+      else if (!(r->err[i] <= ldexp(r->T, -r->lvl[i])) && (aI + r->err[i] == aI))
+        r->stats[GMO_ST_ROUNDOFF]++;
+      if (r->keep_leaves && leaf_push(r, r->c + i * d, r->h + i * d, r->lvl[i])) return GMO_ENOMEM;
+    }
+  }
+  nc_ = (double*)malloc(sizeof(double) * n2 * d);
+  nh_ = (double*)malloc(sizeof(double) * n2 * d);
+  nl_ = (int32_t*)malloc(sizeof(int32_t) * n2);
+  if (!nc_ || !nh_ || !nl_) {
+    free(nc_);
+    free(nh_);
+    free(nl_);
+    return GMO_ENOMEM;
+  }
+  for (i = 0; i < r->n; ++i) {
+    if (r->fin[i]) continue;
+    {
+      int k = r->axis[i];
+      double hp = r->h[i * d + k] * 0.5;
+      memcpy(nc_ + p * d, r->c + i * d, sizeof(double) * d);
+      memcpy(nh_ + p * d, r->h + i * d, sizeof(double) * d);
+      memcpy(nc_ + (nk + p) * d, r->c + i * d, sizeof(double) * d);
+      memcpy(nh_ + (nk + p) * d, r->h + i * d, sizeof(double) * d);
+      nc_[p * d + k] = r->c[i * d + k] - hp;
+      nc_[(nk + p) * d + k] = r->c[i * d + k] + hp;
+      nh_[p * d + k] = hp;
+      nh_[(nk + p) * d + k] = hp;
+      nl_[p] = r->lvl[i] + 1;
+      nl_[nk + p] = r->lvl[i] + 1;
+      p++;
+    }
+  }
+  if (grow(r, n2)) {
+    free(nc_);
+    free(nh_);
+    free(nl_);
+    return GMO_ENOMEM;
+  }
+  memcpy(r->c, nc_, sizeof(double) * n2 * d);
+  memcpy(r->h, nh_, sizeof(double) * n2 * d);
+  memcpy(r->lvl, nl_, sizeof(int32_t) * n2);
+  free(nc_);
+  free(nh_);
+  free(nl_);
+  r->n = n2;
+  return GMO_RUNNING;
+}
+
+int gmo_step(gmo_run* r) {
+  int st;
+  if (r->status != GMO_RUNNING) return r->status;
+  st = phase_eval(r);
+  if (st != GMO_RUNNING) return st;
+  if (2 * r->n_keep > r->max_regions) {
+    r->status = GMO_MAX_REGIONS;
+    return r->status;
+  }
+  st = phase_split(r);
+  if (st != GMO_RUNNING) r->status = st;
+  return r->status;
+}
+
+int gmo_run_to_end(gmo_run* r) {
+  while (r->status == GMO_RUNNING) gmo_step(r);
+  return r->status;
+}
+
+void gmo_result(const gmo_run* r, double* I, double* E, int* status, int64_t* stats) {
+  *I = r->I;
+  *E = r->E;
+  *status = r->status;
+  memcpy(stats, r->stats, sizeof r->stats);
+}
+
+int64_t gmo_active_count(const gmo_run* r) { return r->n; }
+
+void gmo_get_active(const gmo_run* r, double* c, double* h, int32_t* lvl, double* Q, double* err,
+                    int32_t* axis) {
+  int64_t n = r->n;
+  int d = r->d;
+  if (c) memcpy(c, r->c, sizeof(double) * n * d);
+  if (h) memcpy(h, r->h, sizeof(double) * n * d);
+  if (lvl) memcpy(lvl, r->lvl, sizeof(int32_t) * n);
+  if (Q) memcpy(Q, r->Q, sizeof(double) * n);
+  if (err) memcpy(err, r->err, sizeof(double) * n);
+  if (axis) memcpy(axis, r->axis, sizeof(int32_t) * n);
+}
+
+int64_t gmo_leaf_count(const gmo_run* r) { return r->nleaf + r->n; }
+
+void gmo_get_leaves(const gmo_run* r, double* c, double* h, int32_t* lvl) {
+  int d = r->d;
+  memcpy(c, r->lc, sizeof(double) * r->nleaf * d);
+  memcpy(h, r->lh, sizeof(double) * r->nleaf * d);
+  memcpy(lvl, r->llvl, sizeof(int32_t) * r->nleaf);
+  memcpy(c + r->nleaf * d, r->c, sizeof(double) * r->n * d);
+  memcpy(h + r->nleaf * d, r->h, sizeof(double) * r->n * d);
+  memcpy(lvl + r->nleaf, r->lvl, sizeof(int32_t) * r->n);
+}
+
+int64_t gmo_trace_len(const gmo_run* r) { return r->ntr; }
+
+void gmo_get_trace(const gmo_run* r, int64_t* counts, double* IE) {
+  memcpy(counts, r->trc, sizeof(int64_t) * 2 * r->ntr);
+  memcpy(IE, r->trv, sizeof(double) * 2 * r->ntr);
+}
+
+void gmo_free(gmo_run* r) {
+  if (!r) return;
+  free(r->c);
+  free(r->h);
+  free(r->Q);
+  free(r->err);
+  free(r->lvl);
+  free(r->axis);
+  free(r->geo);
+  free(r->fin);
+  free(r->lc);
+  free(r->lh);
+  free(r->llvl);
+  free(r->trc);
+  free(r->trv);
+  free(r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fixed-tree quadrature and its gradient.                                   */
+/* The gradient is the exact derivative of sum_leaves vol * sum_n w_n f(x_n) */
+/* with the tree held fixed: sum_leaves vol * sum_n w_n df/dtheta(x_n).      */
+/* ------------------------------------------------------------------------ */
+int gmo_quad_leaves(int fam, int d, const double* params, int64_t n, const double* c,
+                    const double* h, const int32_t* lvl, double vol_omega, double* out_q) {
+  ksum s = {0.0, 0.0};
+  double out[16 + 32];
+  int64_t i;
+  int st = 0;
+  for (i = 0; i < n; ++i) {
+    if (gmo_rule(fam, d, params, c + i * d, h + i * d, lvl[i], vol_omega, out)) st = GMO_NONFINITE;
+    ks_add(&s, out[0]);
+  }
+  *out_q = ks_val(&s);
+  return st;
+}
+
+typedef struct {
+  int fam, d;
+  const double* p;
+  double w[5];
+  ksum g[32];
+} grad_ctx;
+
+static void grad_cb(void* pp, int cls, const double* x) {
+  grad_ctx* q = (grad_ctx*)pp;
+  double df[32];
+  int j;
+  gmo_df(q->fam, q->d, q->p, x, df);
+  for (j = 0; j < 2 * q->d; ++j) ks_add(&q->g[j], q->w[cls - 1] * df[j]);
+}
+
+int gmo_grad_leaves(int fam, int d, const double* params, int64_t n, const double* c,
+                    const double* h, const int32_t* lvl, double vol_omega, double* out_grad) {
+  double lam[5], v[5], e[5];
+  ksum tot[32];
+  int64_t i;
+  int j;
+  grad_ctx q;
+  memset(tot, 0, sizeof tot);
+  memset(&q, 0, sizeof q);
+  q.fam = fam;
+  q.d = d;
+  q.p = params;
+  gmo_constants(d, lam, q.w, v, e);
+  for (i = 0; i < n; ++i) {
+    double vol = ldexp(vol_omega, -lvl[i]);
+    memset(q.g, 0, sizeof q.g);
+    visit_nodes(d, c + i * d, h + i * d, grad_cb, &q);
+    for (j = 0; j < 2 * d; ++j) ks_add(&tot[j], vol * ks_val(&q.g[j]));
+  }
+  for (j = 0; j < 2 * d; ++j) out_grad[j] = ks_val(&tot[j]);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lock-step batch.  Every item runs the loop above with its own tolerance; */
+/* all items step together.  Reading of a shared region budget: when the    */
+/* kept regions of all still-running items would need more than             */
+/* max_regions_total rows after splitting, every still-running item stops    */
+/* with the max-regions status and its current (I, E).  Below that budget    */
+/* each item's result is that of an independent run.                         */
+/* ------------------------------------------------------------------------ */
+int gmo_integrate_batch(int n, const int* fam, const double* params, const int* d,
+                        const double* lo, const double* hi, const double* rel_tol,
+                        const double* abs_tol, int64_t max_regions_total, int init_log2,
+                        int max_iters, double* out_est, double* out_err, int* out_status,
+                        int64_t* out_iters) {
+  gmo_run** runs;
+  int i, worst = 0, running;
+  int64_t po = 0, bo = 0;
+  if (n < 1) return GMO_EINVAL;
+  runs = (gmo_run**)calloc((size_t)n, sizeof(gmo_run*));
+  if (!runs) return GMO_ENOMEM;
+  for (i = 0; i < n; ++i) {
+    int st;
+    runs[i] = gmo_create(fam[i], d[i], params + po, lo + bo, hi + bo, rel_tol[i], abs_tol[i],
+                         max_regions_total, init_log2, max_iters, 0, &st);
+    po += 2 * d[i];
+    bo += d[i];
+    if (!runs[i]) out_status[i] = st;
+  }
+  /* The initial partitions must fit together. */
+  {
+    int64_t tot = 0;
+    for (i = 0; i < n; ++i)
+      if (runs[i]) tot += runs[i]->n;
+    if (tot > max_regions_total) {
+      for (i = 0; i < n; ++i) gmo_free(runs[i]);
+      free(runs);
+      return GMO_EINVAL;
+    }
+  }
+  do {
+    int64_t need = 0;
+    running = 0;
+    for (i = 0; i < n; ++i) {
+      if (!runs[i] || runs[i]->status != GMO_RUNNING) continue;
+      if (phase_eval(runs[i]) == GMO_RUNNING) {
+        need += 2 * runs[i]->n_keep;
+        running++;
+      }
+    }
+    if (running && need > max_regions_total) {
+      for (i = 0; i < n; ++i)
+        if (runs[i] && runs[i]->status == GMO_RUNNING) runs[i]->status = GMO_MAX_REGIONS;
+      running = 0;
+    }
+    for (i = 0; i < n; ++i) {
+      if (!runs[i] || runs[i]->status != GMO_RUNNING) continue;
+      if (phase_split(runs[i]) != GMO_RUNNING) runs[i]->status = GMO_ENOMEM;
+    }
+  } while (running);
+  for (i = 0; i < n; ++i) {
+    if (!runs[i]) {
+      out_est[i] = NAN;
+      out_err[i] = NAN;
+      if (out_iters) out_iters[i] = 0;
+      continue;
+    }
+    out_est[i] = runs[i]->I;
+    out_err[i] = runs[i]->E;
+    out_status[i] = runs[i]->status;
+    if (out_iters) out_iters[i] = runs[i]->iter;
+    if (runs[i]->status > worst) worst = runs[i]->status;
+    gmo_free(runs[i]);
+  }
+  free(runs);
+  return worst;
+}

@@ -1,0 +1,129 @@
+/*
+ * gm_oracle.h -- serial FP64 CPU oracle for adaptive Genz-Malik cubature.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product
+ * (the HIP library behind include/gm.h) never calls it and shares no code,
+ * header, table or constant with it.
+ *
+ * What it computes (Tonarelli et al., "Adaptive Multidimensional Quadrature
+ * on Multi-GPU Systems", arXiv 2511.01573):
+ *   - the fully symmetric Genz-Malik rule and an embedded lower-degree rule
+ *     on a hyper-rectangle (Sec. 2), with a local error estimate (Sec. 2,
+ *     "heuristic estimator") and a fourth-difference split axis (Sec. 2);
+ *   - the breadth-first adaptive loop of Sec. 3 (initial uniform partition,
+ *     evaluate every region, global convergence test of Sec. 4, heuristic
+ *     classifier, split along the chosen axis);
+ *   - the test integrands of Sec. 4 and their seeded Genz-family
+ *     generalisations;
+ *   - the derivative of the fixed-tree quadrature with respect to the
+ *     integrand parameters, and a lock-step batch of independent integrals.
+ *
+ * All floating point is IEEE binary64, built with -ffp-contract=off; every
+ * fused multiply-add is written out as fma().
+ */
+#ifndef GM_ORACLE_H
+#define GM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GMO_OSCILLATORY = 1,
+  GMO_PRODUCT_PEAK = 2,
+  GMO_CORNER_PEAK = 3,
+  GMO_GAUSSIAN = 4,
+  GMO_C0 = 5,
+  GMO_DISCONTINUOUS = 6,
+  GMO_POLY = 7,
+  /* Oracle-only test family: prod_j (x_j - u_j)^k_j with k_j = (int)a_j.
+     Used to pin the rule on monomials; not part of the product's API. */
+  GMO_MONOMIAL = 99
+};
+
+enum {
+  GMO_OK = 0,
+  GMO_MAX_REGIONS = 1,
+  GMO_MAX_ITERS = 2,
+  GMO_PRECISION_LIMIT = 3,
+  GMO_NONFINITE = 4,
+  GMO_EINVAL = -1,
+  GMO_ENOMEM = -2,
+  GMO_RUNNING = 100
+};
+
+/* Stats layout (int64[8]). */
+enum {
+  GMO_ST_ITERS = 0,       /* evaluate steps executed                   */
+  GMO_ST_REGIONS = 1,     /* sum of active-set sizes over iterations    */
+  GMO_ST_EVALS = 2,       /* REGIONS * N(d)                             */
+  GMO_ST_ACTIVE = 3,      /* size of the last evaluated active set      */
+  GMO_ST_FINISHED = 4,    /* regions retired by the classifier          */
+  GMO_ST_MAX_ACTIVE = 5,  /* largest active set                         */
+  GMO_ST_GEOMETRY = 6,    /* regions retired by the geometry guard      */
+  GMO_ST_ROUNDOFF = 7     /* regions retired by the round-off guard     */
+};
+
+int64_t gmo_num_nodes(int d);
+/* lam[5] = {0, l2, l3, l4, l5}; w[5], v[5] and e[5] = w - v, classes 1..5. */
+void gmo_constants(int d, double lam[5], double w[5], double v[5], double e[5]);
+/* All N(d) nodes of the region (c, h) in visit order: x[N*d], cls[N] in 1..5. */
+void gmo_nodes(int d, const double* c, const double* h, double* x, int* cls);
+/* Integrand value at x; params = a[0..d), u[0..d). */
+double gmo_f(int fam, int d, const double* params, const double* x);
+/* Gradient of f at x with respect to params (out[2d]); returns f. */
+double gmo_df(int fam, int d, const double* params, const double* x, double* out);
+
+/*
+ * One region.  out layout (double):
+ *   [0] Q   [1] err   [2] axis   [3] geometry flag (0/1)
+ *   [4] scaleQ = vol * sum_k |w_k| Sabs_k
+ *   [5] scaleE = vol * sum_k |e_k| Sabs_k
+ *   [6..11) S_1..S_5     [11..16) Sabs_1..Sabs_5
+ *   [16..16+d) D_0..D_{d-1}
+ * Returns 0, or GMO_NONFINITE if some f value or class sum is not finite.
+ */
+int gmo_rule(int fam, int d, const double* params, const double* c, const double* h,
+             int lvl, double vol_omega, double* out);
+
+/* Adaptive run (handle API). */
+typedef struct gmo_run gmo_run;
+gmo_run* gmo_create(int fam, int d, const double* params, const double* lo, const double* hi,
+                    double rel_tol, double abs_tol, int64_t max_regions, int init_log2,
+                    int max_iters, int keep_leaves, int* status);
+/* One full iteration; returns GMO_RUNNING or the final status. */
+int gmo_step(gmo_run* r);
+int gmo_run_to_end(gmo_run* r);
+void gmo_result(const gmo_run* r, double* I, double* E, int* status, int64_t* stats);
+int64_t gmo_active_count(const gmo_run* r);
+/* Last evaluated active set (c, h: n*d row-major; lvl; Q; err; axis). */
+void gmo_get_active(const gmo_run* r, double* c, double* h, int32_t* lvl, double* Q,
+                    double* err, int32_t* axis);
+int64_t gmo_leaf_count(const gmo_run* r);
+/* Frozen tree: retired leaves followed by the last evaluated active set. */
+void gmo_get_leaves(const gmo_run* r, double* c, double* h, int32_t* lvl);
+/* Per-iteration trace, int64 [iters][2] = (n_active, n_finished) and
+   double [iters][2] = (I, E). */
+int64_t gmo_trace_len(const gmo_run* r);
+void gmo_get_trace(const gmo_run* r, int64_t* counts, double* IE);
+void gmo_free(gmo_run* r);
+
+/* Fixed-tree quadrature and its parameter gradient over a leaf list. */
+int gmo_quad_leaves(int fam, int d, const double* params, int64_t n, const double* c,
+                    const double* h, const int32_t* lvl, double vol_omega, double* out_q);
+int gmo_grad_leaves(int fam, int d, const double* params, int64_t n, const double* c,
+                    const double* h, const int32_t* lvl, double vol_omega, double* out_grad);
+
+/* Lock-step batch of independent integrals sharing one region capacity. */
+int gmo_integrate_batch(int n, const int* fam, const double* params, const int* d,
+                        const double* lo, const double* hi, const double* rel_tol,
+                        const double* abs_tol, int64_t max_regions_total, int init_log2,
+                        int max_iters, double* out_est, double* out_err, int* out_status,
+                        int64_t* out_iters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
