@@ -1,0 +1,198 @@
+/*
+ * gm.h -- C ABI of libgm, adaptive Genz-Malik cubature on AMD Instinct MI355X
+ * (gfx950), FP64.
+ *
+ * Method: Tonarelli, Riva, Benedusi, Ferrandi, Krause, "Adaptive
+ * Multidimensional Quadrature on Multi-GPU Systems", arXiv 2511.01573.
+ *   Sec. 2  - the fully symmetric Genz-Malik rule, its embedded lower-degree
+ *             rule and the |Q7 - Q5| local error estimate; the split axis
+ *             from per-axis fourth differences.
+ *   Sec. 3  - breadth-first adaptivity: every region is evaluated each
+ *             iteration, the global estimate is checked, regions with a
+ *             negligible error share are retired by a classifier and the rest
+ *             are halved along their axis; region data stays on the device
+ *             in structure-of-arrays form; filtering and splitting are fused.
+ *   Sec. 4  - the stopping rule  E <= max(abs_tol, rel_tol * |I|)  (the
+ *             paper uses abs_tol = 1e-16) and the test integrands.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are HOST pointers unless stated otherwise.  The
+ *     caller owns them; the library keeps no pointer after a call returns
+ *     (except a workspace registered with gm_set_workspace).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *     of a call is enqueued on it and the call returns after its results are
+ *     final (host-synchronous).
+ *   - params layout for every integrand: double[2d] = a[0..d), u[0..d).
+ *   - Return value: a status code below.  On a negative code the outputs are
+ *     left untouched.
+ *   - Calls on one process are serialised by an internal mutex; they are not
+ *     reentrant from device callbacks.
+ */
+#ifndef GM_H
+#define GM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Integrands on a box, parameters a, u (Sec. 4 and their Genz families):
+ *   1 oscillatory   cos(2 pi u_0 + sum a_j x_j)               (paper f1: a_j = j, u = 0)
+ *   2 product peak  prod 1 / (a_j^-2 + (x_j - u_j)^2)          (f2: a = 50, u = 1/2)
+ *   3 corner peak   (1 + sum a_j x_j)^-(d+1)                   (f3: a_j = j)
+ *   4 Gaussian      exp(-sum a_j^2 (x_j - u_j)^2)              (f4: a = 25, u = 1/2)
+ *   5 C0            exp(-sum a_j |x_j - u_j|)                  (f5: a = 10, u = 1/2)
+ *   6 discontinuous 0 if x_j > u_j for any j, else exp(sum a_j x_j)
+ *                                                  (f6: a_j = j + 4, u_j = (3 + j)/10)
+ *   7 polynomial    (sum x_j^2)^11                             (f7; params ignored) */
+enum {
+  GM_OSCILLATORY = 1,
+  GM_PRODUCT_PEAK = 2,
+  GM_CORNER_PEAK = 3,
+  GM_GAUSSIAN = 4,
+  GM_C0 = 5,
+  GM_DISCONTINUOUS = 6,
+  GM_POLY_F7 = 7
+};
+
+/* Status codes. */
+enum {
+  GM_OK = 0,              /* E <= max(abs_tol, rel_tol |I|)                               */
+  GM_MAX_REGIONS = 1,     /* splitting would exceed the region capacity; best (I, E) out  */
+  GM_MAX_ITERS = 2,       /* iteration budget (option max_iters) used up; (I, E) out      */
+  GM_PRECISION_LIMIT = 3, /* every region retired by a guard while E > T; (I, E) out      */
+  GM_NONFINITE = 4,       /* f (or a rule sum) was NaN/Inf somewhere; outputs are NaN     */
+  GM_EINVAL = -1,         /* invalid argument; nothing ran                                */
+  GM_ENOMEM = -2,         /* device memory (or the registered workspace) too small        */
+  GM_EHIP = -3            /* HIP runtime error; see gm_status_string(GM_EHIP)              */
+};
+
+/*
+ * gm_integrate -- integrate f over the box [lo, hi] (Sec. 3 loop).
+ *   integrand_id  one of GM_OSCILLATORY .. GM_POLY_F7
+ *   params        double[2d] (a, u), finite
+ *   d             2 <= d <= 16
+ *   lo, hi        double[d], finite, lo[j] < hi[j]
+ *   rel_tol       >= 0, abs_tol >= 0, finite, not both 0
+ *   max_regions   capacity of the active region set; must hold the initial
+ *                 partition (2^(d*floor(L0/d)) regions, L0 = option
+ *                 init_log2_regions, default 12)
+ *   out_est, out_err  host double*: I and E
+ * Returns GM_OK .. GM_NONFINITE, or a negative error.
+ */
+int gm_integrate(int integrand_id, const double* params, int d, const double* lo, const double* hi,
+                 double rel_tol, double abs_tol, int64_t max_regions, double* out_est,
+                 double* out_err, void* stream);
+
+/*
+ * gm_integrate_batch -- n independent integrals in one lock-stepped,
+ * device-resident region store (thousands of small integrals at once).
+ *   integrand_ids int[n]; d int[n] (2..16)
+ *   params        packed: item i contributes 2*d[i] doubles (a then u)
+ *   lo, hi        packed: item i contributes d[i] doubles each
+ *   rel_tol, abs_tol double[n]
+ *   max_regions_total  shared capacity of all items' active regions
+ *   out_est, out_err double[n], out_status int[n]
+ * Item i follows exactly the loop of gm_integrate with its own tolerance; all
+ * items advance one iteration together.  If the kept regions of all still
+ * running items would need more than max_regions_total rows, every still
+ * running item stops with GM_MAX_REGIONS and its current (I, E).  An invalid
+ * item gets GM_EINVAL in out_status and NaN outputs; the call returns the
+ * largest non-negative item status, or a negative code for a call-level fault.
+ */
+int gm_integrate_batch(int n, const int* integrand_ids, const double* params, const int* d,
+                       const double* lo, const double* hi, const double* rel_tol,
+                       const double* abs_tol, int64_t max_regions_total, double* out_est,
+                       double* out_err, int* out_status, void* stream);
+
+/*
+ * gm_integrate_grad -- gm_integrate plus the gradient of the estimate with
+ * respect to params, out_grad double[2d] in the params layout.  The gradient
+ * is the exact derivative of the fixed-tree quadrature: the region tree the
+ * forward run ended with (retired leaves plus the last active set) is frozen
+ * and sum_leaves vol * sum_nodes w * df/dtheta is evaluated by an adjoint
+ * kernel.  Discontinuity locations (u of the discontinuous family) get 0.
+ */
+int gm_integrate_grad(int integrand_id, const double* params, int d, const double* lo,
+                      const double* hi, double rel_tol, double abs_tol, int64_t max_regions,
+                      double* out_est, double* out_err, double* out_grad, void* stream);
+
+/*
+ * gm_eval_regions -- the rule kernel alone on a caller-given region list
+ * (Sec. 2: rule value, error estimate and split axis of each region).
+ *   c, h        host double[n*d], row-major: region r is prod_j [c - h, c + h]
+ *   lvl         host int32[n]: region volume = vol(box [lo, hi]) * 2^-lvl
+ *   out_q, out_err  host double[n]; out_axis host int32[n] (bit 7 set when
+ *               halving along the axis would not change the region)
+ */
+int gm_eval_regions(int integrand_id, const double* params, int d, const double* lo,
+                    const double* hi, int64_t n, const double* c, const double* h,
+                    const int32_t* lvl, double* out_q, double* out_err, int32_t* out_axis,
+                    void* stream);
+
+/*
+ * gm_set_workspace -- register a caller-owned DEVICE buffer (e.g. a torch
+ * uint8 tensor) used for all device scratch instead of library allocations.
+ * bytes == 0 (or ptr == NULL) returns to library-owned memory.  The caller
+ * keeps the buffer alive while registered; the library never frees it.
+ * Calls needing more than `bytes` return GM_ENOMEM.
+ */
+int gm_set_workspace(void* device_ptr, size_t bytes);
+
+/* Bytes of device workspace one call needs: mode 0 integrate, 1 grad (without
+   the leaf store, which grows on demand), 2 batch (d = max item dimension). */
+size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
+
+/*
+ * gm_set_option -- process-wide knobs.  Returns GM_OK or GM_EINVAL.
+ *   "init_log2_regions"  L0, initial partition 2^(d*floor(L0/d)) cells (default 12, 0..30)
+ *   "max_iters"          iteration budget (default 10000, >= 1)
+ *   "graph_iters"        iterations per hipGraph replay, 0 = launch kernels
+ *                        directly with a host check every iteration (default 0)
+ *   "lanes_per_region"   0 = automatic, else 1..64 power of two (rule kernel mapping)
+ *   "timing"             1 = record per-phase device time with hipEvents (default 0)
+ *   "log"                1 = print one line per iteration to stderr (default 0)
+ */
+int gm_set_option(const char* key, int64_t value);
+
+/* Human-readable text of a status code (the last HIP error text for GM_EHIP). */
+const char* gm_status_string(int status);
+
+/* Statistics of the last completed call. */
+typedef struct {
+  int64_t iterations;        /* evaluate steps executed                           */
+  int64_t regions_evaluated; /* sum over iterations of the active-set size         */
+  int64_t evals;             /* integrand evaluations (regions * N(d))              */
+  int64_t max_active;        /* largest active set                                 */
+  int64_t final_active;      /* active regions in the last evaluated set            */
+  int64_t finished;          /* regions retired by the classifier                   */
+  int64_t status;            /* status of the call                                 */
+  int64_t lanes_per_region;  /* rule-kernel mapping used in the last iteration      */
+  double rule_ms;            /* device time in the rule kernel (option timing)      */
+  double reduce_ms;          /* global reduction + convergence test                 */
+  double classify_ms;        /* classify + block counts                             */
+  double split_ms;           /* scan + split + compaction                           */
+  double total_ms;           /* wall time of the call                               */
+  int64_t rule_launches;     /* number of rule-kernel launches timed                */
+} gm_stats;
+
+int gm_last_stats(gm_stats* out);
+
+/* Number of integrand nodes per region, 2^d + 2 d^2 + 2 d + 1. */
+int64_t gm_num_nodes(int d);
+
+/*
+ * gm_last_active -- copy out the last evaluated active set of the most recent
+ * gm_integrate / gm_integrate_grad call (introspection for parity checks).
+ * Copies min(n, count) regions; c, h host double[n*d] row-major, lvl int32[n],
+ * q, err double[n], axis int32[n]; any pointer may be NULL.  Returns the count.
+ */
+int64_t gm_last_active(int64_t n, double* c, double* h, int32_t* lvl, double* q, double* err,
+                       int32_t* axis);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -397,11 +397,15 @@ struct gmo_run {
   int iter;
   int64_t n;   /* active count */
   int64_t cap; /* allocated rows */
-  double *c, *h, *Q, *err;
+  double *c, *h, *Q, *err, *escl;
   int32_t *lvl, *axis;
   unsigned char *geo, *fin;
   double I, E, T;
   ksum Ifin, Efin;
+  /* test diagnostic: sum over the frozen tree of vol * sum_k |w_k - v_k| Sabs_k,
+     the magnitude the error estimates cancel (sets parity tolerances on E) */
+  ksum Sfin;
+  double Escale;
   int64_t n_keep;
   int64_t stats[8];
   /* leaves */
@@ -423,11 +427,12 @@ static int grow(gmo_run* r, int64_t need) {
   r->h = (double*)realloc(r->h, sizeof(double) * nc * r->d);
   r->Q = (double*)realloc(r->Q, sizeof(double) * nc);
   r->err = (double*)realloc(r->err, sizeof(double) * nc);
+  r->escl = (double*)realloc(r->escl, sizeof(double) * nc);
   r->lvl = (int32_t*)realloc(r->lvl, sizeof(int32_t) * nc);
   r->axis = (int32_t*)realloc(r->axis, sizeof(int32_t) * nc);
   r->geo = (unsigned char*)realloc(r->geo, nc);
   r->fin = (unsigned char*)realloc(r->fin, nc);
-  if (!r->c || !r->h || !r->Q || !r->err || !r->lvl || !r->axis || !r->geo || !r->fin) return -1;
+  if (!r->c || !r->h || !r->Q || !r->err || !r->escl || !r->lvl || !r->axis || !r->geo || !r->fin) return -1;
   r->cap = nc;
   return 0;
 }
@@ -544,11 +549,17 @@ static int phase_eval(gmo_run* r) {
     }
     r->Q[i] = out[0];
     r->err[i] = out[1];
+    r->escl[i] = out[5];
     r->axis[i] = (int32_t)out[2];
     r->geo[i] = (unsigned char)out[3];
   }
   for (i = 0; i < r->n; ++i) ks_add(&Is, r->Q[i]);
   for (i = 0; i < r->n; ++i) ks_add(&Es, r->err[i]);
+  {
+    ksum Ss = r->Sfin;
+    for (i = 0; i < r->n; ++i) ks_add(&Ss, r->escl[i]);
+    r->Escale = ks_val(&Ss);
+  }
   r->I = ks_val(&Is);
   r->E = ks_val(&Es);
   r->T = fmax(r->abs_tol, r->rel_tol * fabs(r->I));
@@ -594,6 +605,7 @@ static int phase_split(gmo_run* r) {
     if (r->fin[i]) {
       ks_add(&r->Ifin, r->Q[i]);
       ks_add(&r->Efin, r->err[i]);
+      ks_add(&r->Sfin, r->escl[i]);
       r->stats[GMO_ST_FINISHED]++;
       if (r->geo[i]) r->stats[GMO_ST_GEOMETRY]++;
       else if (!(r->err[i] <= ldexp(r->T, -r->lvl[i])) && (aI + r->err[i] == aI))
@@ -672,6 +684,8 @@ void gmo_result(const gmo_run* r, double* I, double* E, int* status, int64_t* st
 
 int64_t gmo_active_count(const gmo_run* r) { return r->n; }
 
+double gmo_escale(const gmo_run* r) { return r->Escale; }
+
 void gmo_get_active(const gmo_run* r, double* c, double* h, int32_t* lvl, double* Q, double* err,
                     int32_t* axis) {
   int64_t n = r->n;
@@ -709,6 +723,7 @@ void gmo_free(gmo_run* r) {
   free(r->h);
   free(r->Q);
   free(r->err);
+  free(r->escl);
   free(r->lvl);
   free(r->axis);
   free(r->geo);

@@ -98,6 +98,9 @@ int gmo_step(gmo_run* r);
 int gmo_run_to_end(gmo_run* r);
 void gmo_result(const gmo_run* r, double* I, double* E, int* status, int64_t* stats);
 int64_t gmo_active_count(const gmo_run* r);
+/* Test diagnostic: sum over the frozen tree of vol * sum_k |w_k - v_k| Sabs_k
+   (the magnitude that the error estimates cancel), for parity bounds on E. */
+double gmo_escale(const gmo_run* r);
 /* Last evaluated active set (c, h: n*d row-major; lvl; Q; err; axis). */
 void gmo_get_active(const gmo_run* r, double* c, double* h, int32_t* lvl, double* Q,
                     double* err, int32_t* axis);

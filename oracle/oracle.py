@@ -75,6 +75,8 @@ def lib():
         L.gmo_run_to_end.restype = C.c_int
         L.gmo_run_to_end.argtypes = [C.c_void_p]
         L.gmo_result.argtypes = [C.c_void_p, dp, dp, ip, i64p]
+        L.gmo_escale.restype = C.c_double
+        L.gmo_escale.argtypes = [C.c_void_p]
         L.gmo_active_count.restype = C.c_int64
         L.gmo_active_count.argtypes = [C.c_void_p]
         L.gmo_get_active.argtypes = [C.c_void_p, dp, dp, i32p, dp, dp, i32p]
@@ -231,7 +233,8 @@ class Run:
         stats = np.zeros(8, dtype=np.int64)
         lib().gmo_result(self.h, C.byref(I), C.byref(E), C.byref(st),
                          stats.ctypes.data_as(C.POINTER(C.c_int64)))
-        out = {"I": I.value, "E": E.value, "status": st.value}
+        out = {"I": I.value, "E": E.value, "status": st.value,
+               "escale": float(lib().gmo_escale(self.h))}
         out.update({k: int(v) for k, v in zip(STAT_NAMES, stats)})
         return out
 

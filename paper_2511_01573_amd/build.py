@@ -1,0 +1,82 @@
+"""Build libgm.so (HIP, gfx950) in-tree.
+
+The rule kernel is compiled once per integrand family (-DGM_RULE_FAMILY=k) so
+the objects build in parallel; everything links into
+paper_2511_01573_amd/libgm.so.  Flags: FP64 code with no implicit FMA
+contraction (-ffp-contract=off; fused multiply-adds are written explicitly),
+packed-FP32 instructions disabled.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import glob
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libgm.so")
+ROOT = os.path.dirname(PKG)
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-ffp-contract=off", "-fPIC", "-Wall",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+FAMILIES = range(1, 8)
+
+
+def _units():
+    units = []
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        name = os.path.splitext(os.path.basename(src))[0]
+        if name == "gm_rule":
+            for f in FAMILIES:
+                units.append((src, os.path.join(BUILD, f"{name}_f{f}.o"), [f"-DGM_RULE_FAMILY={f}"]))
+        else:
+            units.append((src, os.path.join(BUILD, f"{name}.o"), []))
+    return units
+
+
+def _headers_mtime():
+    hs = glob.glob(os.path.join(CSRC, "*.hpp")) + [os.path.join(ROOT, "include", "gm.h")]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(unit, force):
+    src, obj, extra = unit
+    if not force and os.path.exists(obj):
+        if os.path.getmtime(obj) >= max(os.path.getmtime(src), _headers_mtime()):
+            return obj, None
+    cmd = [HIPCC] + FLAGS + extra + ["-c", src, "-o", obj]
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    errs = "\n".join(l for l in (p.stdout + p.stderr).splitlines() if "packed-fp32-ops" not in l)
+    if p.returncode != 0:
+        return obj, f"compile failed: {' '.join(cmd)}\n{errs}"
+    return obj, None
+
+
+def build(force: bool = True, jobs: int | None = None) -> str:
+    """Compile every HIP translation unit for gfx950 and link libgm.so."""
+    os.makedirs(BUILD, exist_ok=True)
+    units = _units()
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda u: _compile(u, force), units))
+    errors = [e for _, e in results if e]
+    if errors:
+        raise RuntimeError("\n\n".join(errors))
+    objs = [o for o, _ in results]
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    subprocess.run(cmd, check=True)
+    shutil.move(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    force = "--incremental" not in sys.argv
+    print(build(force=force))

@@ -1,0 +1,1005 @@
+// gm_api.hip -- libgm host driver (the C ABI of include/gm.h) and the control
+// kernels of the breadth-first adaptive loop (arXiv 2511.01573, Sec. 3):
+//
+//   init      initial uniform partition into SoA storage
+//   rule      (gm_rule.hip) Q, err, split axis of every active region
+//   reduce    I = I_fin + sum Q, E = E_fin + sum err, T, stopping rule (Sec. 4)
+//   classify  retire regions whose error share is negligible (+ guards),
+//             per-tile keep counts and retired partial sums
+//   scan      tile offsets of the kept regions; commit the retired sums
+//   scatter   halve every kept region along its axis into the other
+//             ping-pong buffer, stable order (child "-" at rank p, child "+"
+//             at n_keep + p); retired leaves appended in gradient mode
+//
+// All iteration state lives in a device Status block; kernels read the active
+// count and the ping-pong index from it and return at once when a final
+// status is set, so an iteration is a fixed sequence of launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gm.h"
+#include "gm_common.hpp"
+#include "gm_internal.hpp"
+
+namespace gm {
+
+// ---------------------------------------------------------------------------
+// Control kernels.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 1024;        // regions per classify/scatter tile
+constexpr int kTileThreads = 256;  // 4 regions per thread per tile
+constexpr int kMaxRuleGrid = 16384;
+constexpr int kMaxTileGrid = 8192;
+
+struct InitArgs {
+  double* C;
+  double* H;
+  uint16_t* L;
+  int64_t cap;
+  int64_t n0;
+  int d;
+  int m;  // cells per axis = 2^m
+  double lo[kMaxDim];
+  double half[kMaxDim];  // (hi - lo) / 2
+};
+
+__global__ void init_kernel(InitArgs A) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t mask = ((int64_t)1 << A.m) - 1;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < A.n0; t += stride) {
+    for (int j = 0; j < A.d; ++j) {
+      const int64_t kj = (t >> (A.m * j)) & mask;
+      const double hj = ldexp(A.half[j], -A.m);
+      A.H[j * A.cap + t] = hj;
+      A.C[j * A.cap + t] = fma((double)(2 * kj + 1), hj, A.lo[j]);
+    }
+    A.L[t] = (uint16_t)(A.m * A.d);
+  }
+}
+
+// Global reduction of the rule kernel's block partials and the stopping rule.
+__global__ __launch_bounds__(1024) void reduce_kernel(Status* st, const double* partials, int np) {
+  if (st->done) return;
+  dd q = {0.0, 0.0}, e = {0.0, 0.0};
+  for (int p = threadIdx.x; p < np; p += 1024) {
+    q = dd_sum(q, dd{partials[4 * p + 0], partials[4 * p + 1]});
+    e = dd_sum(e, dd{partials[4 * p + 2], partials[4 * p + 3]});
+  }
+  q = wave_sum_dd(q);
+  e = wave_sum_dd(e);
+  __shared__ dd sq[16], se[16];
+  if ((threadIdx.x & 63) == 0) {
+    sq[threadIdx.x >> 6] = q;
+    se[threadIdx.x >> 6] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < 16; ++w) {
+    q = dd_sum(q, sq[w]);
+    e = dd_sum(e, se[w]);
+  }
+  q = dd_sum(q, dd{st->ifin_hi, st->ifin_lo});
+  e = dd_sum(e, dd{st->efin_hi, st->efin_lo});
+  const double I = dd_val(q), E = dd_val(e);
+  const int64_t n = st->n_active;
+  st->iter += 1;
+  st->regions_evaluated += n;
+  if (n > st->max_active) st->max_active = n;
+  if (st->nonfinite) {
+    st->I = NAN;
+    st->E = NAN;
+    st->status = GM_NONFINITE;
+    st->done = 1;
+    return;
+  }
+  const double T = fmax(st->abs_tol, st->rel_tol * fabs(I));
+  st->I = I;
+  st->E = E;
+  st->T = T;
+  if (E <= T) {
+    st->status = GM_OK;
+    st->done = 1;
+  } else if (st->iter >= st->max_iters) {
+    st->status = GM_MAX_ITERS;
+    st->done = 1;
+  }
+}
+
+struct ClassifyArgs {
+  Status* st;
+  const uint16_t* L[2];
+  const double* Q;
+  const double* ERR;
+  const uint8_t* AXIS;
+  uint8_t* FLAG;  // 1 = retired
+  int64_t* TK;    // kept per tile
+  double* TQ;     // retired Q per tile (double-double)
+  double* TE;     // retired err per tile
+};
+
+// Classifier (reading of Sec. 3's "discards subregions whose contribution to
+// the error is negligible"): retire when err <= T * 2^-lvl (the region's
+// error density is within the global budget), when |I| + err == |I|
+// (round-off guard), or when halving along the axis changes nothing
+// (geometry guard, flagged by the rule kernel in bit 7 of the axis byte).
+__global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) {
+  const Status* st = A.st;
+  if (st->done) return;
+  const int64_t n = st->n_active;
+  const double T = st->T;
+  const double aI = fabs(st->I);
+  const uint16_t* __restrict__ L = A.L[st->buf];
+  const int64_t nt = (n + kTile - 1) / kTile;
+  __shared__ int64_t sk[kTileThreads / 64];
+  __shared__ dd sq[kTileThreads / 64], se[kTileThreads / 64];
+  for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    int64_t keep = 0;
+    dd q = {0.0, 0.0}, e = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kTile / kTileThreads; ++k) {
+      const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
+      if (r < n) {
+        const double err = A.ERR[r];
+        const bool fin = (err <= ldexp(T, -(int)L[r])) || (aI + err == aI) || (A.AXIS[r] & 0x80);
+        A.FLAG[r] = fin ? 1 : 0;
+        if (fin) {
+          dd_add(q, A.Q[r]);
+          dd_add(e, err);
+        } else {
+          keep += 1;
+        }
+      }
+    }
+    keep = wave_sum_i64(keep);
+    q = wave_sum_dd(q);
+    e = wave_sum_dd(e);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      sk[w] = keep;
+      sq[w] = q;
+      se[w] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t kk = sk[0];
+      dd tq = sq[0], te = se[0];
+      for (int i = 1; i < kTileThreads / 64; ++i) {
+        kk += sk[i];
+        tq = dd_sum(tq, sq[i]);
+        te = dd_sum(te, se[i]);
+      }
+      A.TK[tile] = kk;
+      A.TQ[2 * tile] = tq.hi;
+      A.TQ[2 * tile + 1] = tq.lo;
+      A.TE[2 * tile] = te.hi;
+      A.TE[2 * tile + 1] = te.lo;
+    }
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of the per-tile keep counts (one workgroup), capacity and
+// precision checks, and the commit of the retired partial sums.
+__global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* TK, int64_t* TOFF,
+                                                    const double* TQ, const double* TE) {
+  if (st->done) return;
+  const int64_t n = st->n_active;
+  const int64_t nt = (n + kTile - 1) / kTile;
+  const int64_t per = (nt + 1023) / 1024;
+  const int64_t t0 = (int64_t)threadIdx.x * per;
+  const int64_t t1 = t0 + per < nt ? t0 + per : nt;
+  int64_t sum = 0;
+  dd q = {0.0, 0.0}, e = {0.0, 0.0};
+  for (int64_t t = t0; t < t1; ++t) {
+    sum += TK[t];
+    q = dd_sum(q, dd{TQ[2 * t], TQ[2 * t + 1]});
+    e = dd_sum(e, dd{TE[2 * t], TE[2 * t + 1]});
+  }
+  // Inclusive scan within the wavefront.
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  __shared__ int64_t wtot[16];
+  __shared__ dd sq[16], se[16];
+  q = wave_sum_dd(q);
+  e = wave_sum_dd(e);
+  if (lane == 63) wtot[w] = inc;
+  if (lane == 0) {
+    sq[w] = q;
+    se[w] = e;
+  }
+  __syncthreads();
+  int64_t woff = 0, total = 0;
+  for (int i = 0; i < 16; ++i) {
+    if (i < w) woff += wtot[i];
+    total += wtot[i];
+  }
+  int64_t run = woff + inc - sum;
+  for (int64_t t = t0; t < t1; ++t) {
+    TOFF[t] = run;
+    run += TK[t];
+  }
+  if (threadIdx.x != 0) return;
+  dd tq = sq[0], te = se[0];
+  for (int i = 1; i < 16; ++i) {
+    tq = dd_sum(tq, sq[i]);
+    te = dd_sum(te, se[i]);
+  }
+  if (total == 0) {
+    st->status = GM_PRECISION_LIMIT;
+    st->done = 1;
+    return;
+  }
+  if (2 * total > st->cap) {
+    st->status = GM_MAX_REGIONS;
+    st->done = 1;
+    return;
+  }
+  const dd fi = dd_sum(dd{st->ifin_hi, st->ifin_lo}, tq);
+  const dd fe = dd_sum(dd{st->efin_hi, st->efin_lo}, te);
+  st->ifin_hi = fi.hi;
+  st->ifin_lo = fi.lo;
+  st->efin_hi = fe.hi;
+  st->efin_lo = fe.lo;
+  st->finished += n - total;
+  st->leaf_base = st->leaf_count;
+  st->leaf_count += n - total;
+  st->n_prev = n;
+  st->n_keep = total;
+  st->n_active = 2 * total;
+  st->buf = 1 - st->buf;
+}
+
+struct ScatterArgs {
+  Status* st;
+  double* C[2];
+  double* H[2];
+  uint16_t* L[2];
+  int64_t cap;
+  const uint8_t* AXIS;
+  const uint8_t* FLAG;
+  int64_t* TOFF;
+  int d;
+  // gradient mode: retired leaves (SoA, capacity leaf_cap)
+  double* LC;
+  double* LH;
+  uint16_t* LL;
+  int64_t leaf_cap;
+};
+
+// Split + stable compaction (Sec. 3: filtering and splitting fused).  Ranks
+// inside a tile come from wavefront ballots and an LDS prefix over the four
+// wavefronts; the tile's base offset comes from the scan kernel.
+__global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
+  const Status* st = A.st;
+  if (st->done) return;
+  const int64_t n = st->n_prev, nk = st->n_keep;
+  const int out = st->buf, in = 1 - out;
+  const int64_t leaf_base = st->leaf_base;
+  const double* __restrict__ Ci = A.C[in];
+  const double* __restrict__ Hi = A.H[in];
+  const uint16_t* __restrict__ Li = A.L[in];
+  double* __restrict__ Co = A.C[out];
+  double* __restrict__ Ho = A.H[out];
+  uint16_t* __restrict__ Lo = A.L[out];
+  const int64_t cap = A.cap;
+  const int64_t nt = (n + kTile - 1) / kTile;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ int64_t wc[kTile / kTileThreads][kTileThreads / 64];
+  for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+    // Counts of every (row, wavefront) first, one barrier per tile.
+    bool keepv[kTile / kTileThreads];
+    uint64_t masks[kTile / kTileThreads];
+#pragma unroll
+    for (int k = 0; k < kTile / kTileThreads; ++k) {
+      const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
+      keepv[k] = (r < n) && (A.FLAG[r] == 0);
+      masks[k] = __ballot(keepv[k]);
+      if (lane == 0) wc[k][w] = __popcll(masks[k]);
+    }
+    __syncthreads();
+    int64_t base = A.TOFF[tile];
+#pragma unroll
+    for (int k = 0; k < kTile / kTileThreads; ++k) {
+      const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
+      int64_t off = base;
+      int64_t rowtot = 0;
+#pragma unroll
+      for (int i = 0; i < kTileThreads / 64; ++i) {
+        if (i < w) off += wc[k][i];
+        rowtot += wc[k][i];
+      }
+      const int64_t before = off + __popcll(masks[k] & ((1ull << lane) - 1ull));
+      if (keepv[k]) {
+        const int64_t p0 = before, p1 = nk + before;
+        const int ax = A.AXIS[r] & 0x7f;
+        for (int j = 0; j < A.d; ++j) {
+          const double cj = Ci[j * cap + r];
+          const double hj = Hi[j * cap + r];
+          if (j == ax) {
+            const double hp = hj * 0.5;
+            Co[j * cap + p0] = cj - hp;
+            Co[j * cap + p1] = cj + hp;
+            Ho[j * cap + p0] = hp;
+            Ho[j * cap + p1] = hp;
+          } else {
+            Co[j * cap + p0] = cj;
+            Co[j * cap + p1] = cj;
+            Ho[j * cap + p0] = hj;
+            Ho[j * cap + p1] = hj;
+          }
+        }
+        const uint16_t l1 = (uint16_t)(Li[r] + 1);
+        Lo[p0] = l1;
+        Lo[p1] = l1;
+      } else if (A.LC != nullptr && r < n) {
+        const int64_t slot = leaf_base + (r - before);
+        if (slot < A.leaf_cap) {
+          for (int j = 0; j < A.d; ++j) {
+            A.LC[j * A.leaf_cap + slot] = Ci[j * cap + r];
+            A.LH[j * A.leaf_cap + slot] = Hi[j * cap + r];
+          }
+          A.LL[slot] = Li[r];
+        }
+      }
+      base += rowtot;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+namespace {
+
+Options g_opt;
+gm_stats g_stats;
+std::string g_hip_err = "no HIP error";
+std::string g_enomem_text;
+
+// Device memory: either the caller's registered workspace or a cached
+// library allocation that only grows.
+void* g_ext_ptr = nullptr;
+size_t g_ext_bytes = 0;
+void* g_own_ptr = nullptr;
+size_t g_own_bytes = 0;
+
+// The last run, for gm_last_active.
+struct LastRun {
+  bool valid = false;
+  int d = 0;
+  int64_t n = 0, cap = 0;
+  Layout lay;
+  int buf = 0;
+} g_last;
+
+int hip_fail(hipError_t e) {
+  g_hip_err = hipGetErrorString(e);
+  (void)hipGetLastError();
+  return GM_EHIP;
+}
+
+#define GM_HIP(call)                      \
+  do {                                    \
+    hipError_t _e = (call);               \
+    if (_e != hipSuccess) return hip_fail(_e); \
+  } while (0)
+
+}  // namespace
+
+Options& options() { return g_opt; }
+
+std::mutex& api_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
+int record_hip_error(hipError_t e) { return hip_fail(e); }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(int d, int64_t cap) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const int64_t ntiles = (cap + kTile - 1) / kTile + 1;
+  for (int b = 0; b < 2; ++b) {
+    L.C[b] = take(sizeof(double) * d * cap);
+    L.H[b] = take(sizeof(double) * d * cap);
+    L.L[b] = take(sizeof(uint16_t) * cap);
+  }
+  L.Q = take(sizeof(double) * cap);
+  L.ERR = take(sizeof(double) * cap);
+  L.AXIS = take(cap);
+  L.FLAG = take(cap);
+  L.TK = take(sizeof(int64_t) * ntiles);
+  L.TOFF = take(sizeof(int64_t) * ntiles);
+  L.TQ = take(sizeof(double) * 2 * ntiles);
+  L.TE = take(sizeof(double) * 2 * ntiles);
+  L.PART = take(sizeof(double) * 4 * kMaxRuleGrid);
+  L.ST = take(sizeof(Status));
+  L.total = off;
+  return L;
+}
+
+int acquire_workspace(size_t bytes, char** base) {
+  if (g_ext_ptr) {
+    if (bytes > g_ext_bytes) return GM_ENOMEM;
+    *base = (char*)g_ext_ptr;
+    return GM_OK;
+  }
+  if (bytes > g_own_bytes) {
+    if (g_own_ptr) {
+      GM_HIP(hipDeviceSynchronize());
+      GM_HIP(hipFree(g_own_ptr));
+      g_own_ptr = nullptr;
+      g_own_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&g_own_ptr, bytes);
+    if (e != hipSuccess) {
+      g_hip_err = hipGetErrorString(e);
+      (void)hipGetLastError();
+      g_own_ptr = nullptr;
+      return GM_ENOMEM;
+    }
+    g_own_bytes = bytes;
+  }
+  *base = (char*)g_own_ptr;
+  return GM_OK;
+}
+
+void fill_consts(int d, RuleConsts& K) {
+  const int64_t D = d;
+  K.lam2 = std::sqrt(9.0 / 70.0);
+  K.lam3 = std::sqrt(9.0 / 10.0);
+  K.lam4 = std::sqrt(9.0 / 10.0);
+  K.lam5 = std::sqrt(9.0 / 19.0);
+  K.w[0] = (double)(400 * D * D - 9120 * D + 12824) / 19683.0;
+  K.w[1] = 980.0 / 6561.0;
+  K.w[2] = (double)(1820 - 400 * D) / 19683.0;
+  K.w[3] = 200.0 / 19683.0;
+  K.w[4] = std::ldexp(6859.0 / 19683.0, -d);
+  K.e[0] = (double)(-19 * (50 * D * D - 870 * D + 361)) / 19683.0;
+  K.e[1] = -4655.0 / 13122.0;
+  K.e[2] = (double)(95 * (20 * D - 37)) / 39366.0;
+  K.e[3] = -475.0 / 19683.0;
+  K.e[4] = K.w[4];
+  K.r7 = 1.0 / 7.0;
+  K.axis_band = 1e-10;
+}
+
+void fill_params(int fam, int d, const double* params, DevParams& P) {
+  std::memset(&P, 0, sizeof P);
+  P.d = d;
+  P.fam = fam;
+  for (int j = 0; j < d; ++j) {
+    P.a[j] = params[j];
+    P.u[j] = params[d + j];
+    P.inv_a2[j] = 1.0 / (P.a[j] * P.a[j]);
+  }
+  P.c0 = 6.283185307179586476925286766559 * P.u[0];
+}
+
+int validate(int fam, const double* params, int d, const double* lo, const double* hi,
+             double rel_tol, double abs_tol) {
+  if (fam < 1 || fam > 7) return GM_EINVAL;
+  if (d < kMinDim || d > kMaxDim) return GM_EINVAL;
+  if (!params || !lo || !hi) return GM_EINVAL;
+  if (!(rel_tol >= 0.0) || !(abs_tol >= 0.0) || !std::isfinite(rel_tol) || !std::isfinite(abs_tol))
+    return GM_EINVAL;
+  if (rel_tol == 0.0 && abs_tol == 0.0) return GM_EINVAL;
+  for (int j = 0; j < d; ++j)
+    if (!std::isfinite(lo[j]) || !std::isfinite(hi[j]) || !(lo[j] < hi[j])) return GM_EINVAL;
+  for (int j = 0; j < 2 * d; ++j)
+    if (!std::isfinite(params[j])) return GM_EINVAL;
+  return GM_OK;
+}
+
+int init_cells_log2(int d) { return g_opt.init_log2 / d; }
+
+hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s) {
+  switch (fam) {
+    case 1: return launch_rule_f1(d, log2l, a, grid, s);
+    case 2: return launch_rule_f2(d, log2l, a, grid, s);
+    case 3: return launch_rule_f3(d, log2l, a, grid, s);
+    case 4: return launch_rule_f4(d, log2l, a, grid, s);
+    case 5: return launch_rule_f5(d, log2l, a, grid, s);
+    case 6: return launch_rule_f6(d, log2l, a, grid, s);
+    case 7: return launch_rule_f7(d, log2l, a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static bool mapping_allowed(int d, int log2l) {
+  if (log2l < 0) return d <= kTprMaxDim;
+  if (log2l == 2) return d >= 6;
+  if (log2l == 4) return d >= 8;
+  if (log2l == 6) return d >= 10;
+  return false;
+}
+
+// Lanes the rule kernel should occupy: 256 CUs x 4 SIMDs x 2 wavefronts x 64.
+constexpr int64_t kTargetLanes = 131072;
+
+int choose_mapping(int d, int64_t n) {
+  const int forced = g_opt.lanes_per_region;
+  if (forced > 0) {
+    int l = -1;
+    if (forced > 1) {
+      l = 0;
+      while ((1 << l) < forced) ++l;
+    }
+    if (mapping_allowed(d, l)) return l;
+  }
+  const int cands[4] = {-1, 2, 4, 6};
+  int best = -2;
+  for (int k = 0; k < 4; ++k) {
+    const int l = cands[k];
+    if (!mapping_allowed(d, l)) continue;
+    best = l;
+    const int64_t lanes = (l < 0) ? n : (n << l);
+    if (lanes >= kTargetLanes) break;
+  }
+  return best;
+}
+
+int rule_grid(int log2l, int64_t n) {
+  const int64_t per_block = (log2l < 0) ? kRuleBlockSize : (kRuleBlockSize >> log2l);
+  const int64_t g = (n + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxRuleGrid));
+}
+
+static int tile_grid_for(int64_t n) {
+  int64_t g = (n + kTile - 1) / kTile;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxTileGrid));
+}
+
+// Leaf store of the gradient mode (SoA, grows on demand).
+struct LeafStore {
+  double* C = nullptr;
+  double* H = nullptr;
+  uint16_t* L = nullptr;
+  int64_t cap = 0;
+  int d = 0;
+  void release() {
+    if (C) (void)hipFree(C);
+    if (H) (void)hipFree(H);
+    if (L) (void)hipFree(L);
+    C = H = nullptr;
+    L = nullptr;
+    cap = 0;
+  }
+};
+
+static LeafStore g_leaves;
+
+LeafView leaf_view() { return LeafView{g_leaves.C, g_leaves.H, g_leaves.L, g_leaves.cap}; }
+
+static int leaf_reserve(int d, int64_t need, int64_t have, hipStream_t s) {
+  if (need <= g_leaves.cap && g_leaves.d == d) return GM_OK;
+  int64_t nc = std::max<int64_t>(need, std::max<int64_t>(1 << 16, 2 * g_leaves.cap));
+  double *C = nullptr, *H = nullptr;
+  uint16_t* L = nullptr;
+  if (hipMalloc(&C, sizeof(double) * d * nc) != hipSuccess ||
+      hipMalloc(&H, sizeof(double) * d * nc) != hipSuccess ||
+      hipMalloc(&L, sizeof(uint16_t) * nc) != hipSuccess) {
+    (void)hipGetLastError();
+    if (C) (void)hipFree(C);
+    if (H) (void)hipFree(H);
+    if (L) (void)hipFree(L);
+    return GM_ENOMEM;
+  }
+  if (have > 0 && g_leaves.d == d) {
+    for (int j = 0; j < d; ++j) {
+      GM_HIP(hipMemcpyAsync(C + j * nc, g_leaves.C + j * g_leaves.cap, sizeof(double) * have,
+                            hipMemcpyDeviceToDevice, s));
+      GM_HIP(hipMemcpyAsync(H + j * nc, g_leaves.H + j * g_leaves.cap, sizeof(double) * have,
+                            hipMemcpyDeviceToDevice, s));
+    }
+    GM_HIP(hipMemcpyAsync(L, g_leaves.L, sizeof(uint16_t) * have, hipMemcpyDeviceToDevice, s));
+    GM_HIP(hipStreamSynchronize(s));
+  }
+  g_leaves.release();
+  g_leaves.C = C;
+  g_leaves.H = H;
+  g_leaves.L = L;
+  g_leaves.cap = nc;
+  g_leaves.d = d;
+  return GM_OK;
+}
+
+// One adaptive run on the device (gm_integrate and the forward pass of
+// gm_integrate_grad).  On return the status block holds the final state.
+int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,
+                 double rel_tol, double abs_tol, int64_t max_regions, hipStream_t s,
+                 bool keep_leaves, RunResult* out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  std::memset(&g_stats, 0, sizeof g_stats);
+  const int m = init_cells_log2(d);
+  const int64_t n0 = (int64_t)1 << (m * d);
+  if (max_regions < n0) return GM_EINVAL;
+  const int64_t cap = max_regions;
+  const Layout lay = make_layout(d, cap);
+  char* base = nullptr;
+  int rc = acquire_workspace(lay.total, &base);
+  if (rc != GM_OK) return rc;
+  g_last.valid = false;
+
+  RuleArgs ra;
+  std::memset(&ra, 0, sizeof ra);
+  fill_params(fam, d, params, ra.P);
+  fill_consts(d, ra.K);
+  for (int b = 0; b < 2; ++b) {
+    ra.C[b] = (const double*)(base + lay.C[b]);
+    ra.H[b] = (const double*)(base + lay.H[b]);
+    ra.L[b] = (const uint16_t*)(base + lay.L[b]);
+  }
+  ra.cap = cap;
+  ra.Q = (double*)(base + lay.Q);
+  ra.ERR = (double*)(base + lay.ERR);
+  ra.AXIS = (uint8_t*)(base + lay.AXIS);
+  ra.partials = (double*)(base + lay.PART);
+  Status* st = (Status*)(base + lay.ST);
+  ra.st = st;
+  double vol = 1.0;
+  for (int j = 0; j < d; ++j) vol = vol * (hi[j] - lo[j]);
+  ra.vol_omega = vol;
+  ra.n_fixed = -1;
+
+  InitArgs ia;
+  std::memset(&ia, 0, sizeof ia);
+  ia.C = (double*)ra.C[0];
+  ia.H = (double*)ra.H[0];
+  ia.L = (uint16_t*)ra.L[0];
+  ia.cap = cap;
+  ia.n0 = n0;
+  ia.d = d;
+  ia.m = m;
+  for (int j = 0; j < d; ++j) {
+    ia.lo[j] = lo[j];
+    ia.half[j] = (hi[j] - lo[j]) * 0.5;
+  }
+
+  ClassifyArgs ca;
+  ca.st = st;
+  ca.L[0] = ra.L[0];
+  ca.L[1] = ra.L[1];
+  ca.Q = ra.Q;
+  ca.ERR = ra.ERR;
+  ca.AXIS = ra.AXIS;
+  ca.FLAG = (uint8_t*)(base + lay.FLAG);
+  ca.TK = (int64_t*)(base + lay.TK);
+  ca.TQ = (double*)(base + lay.TQ);
+  ca.TE = (double*)(base + lay.TE);
+
+  ScatterArgs sa;
+  std::memset(&sa, 0, sizeof sa);
+  sa.st = st;
+  for (int b = 0; b < 2; ++b) {
+    sa.C[b] = (double*)ra.C[b];
+    sa.H[b] = (double*)ra.H[b];
+    sa.L[b] = (uint16_t*)ra.L[b];
+  }
+  sa.cap = cap;
+  sa.AXIS = ra.AXIS;
+  sa.FLAG = ca.FLAG;
+  sa.TOFF = (int64_t*)(base + lay.TOFF);
+  sa.d = d;
+
+  Status hst;
+  std::memset(&hst, 0, sizeof hst);
+  hst.n_active = n0;
+  hst.cap = cap;
+  hst.max_iters = g_opt.max_iters;
+  hst.rel_tol = rel_tol;
+  hst.abs_tol = abs_tol;
+  GM_HIP(hipMemcpyAsync(st, &hst, sizeof hst, hipMemcpyHostToDevice, s));
+  {
+    int g = (int)std::min<int64_t>((n0 + 255) / 256, 4096);
+    hipLaunchKernelGGL(init_kernel, dim3(g), dim3(256), 0, s, ia);
+    GM_HIP(hipGetLastError());
+  }
+
+  hipEvent_t ev[6] = {};
+  const bool timing = g_opt.timing != 0;
+  if (timing)
+    for (auto& e : ev) GM_HIP(hipEventCreate(&e));
+
+  int64_t n = n0;
+  int64_t leaves_have = 0;
+  for (;;) {
+    if (keep_leaves) {
+      // Room for every region of this iteration to retire.
+      rc = leaf_reserve(d, leaves_have + n, leaves_have, s);
+      if (rc != GM_OK) return rc;
+      sa.LC = g_leaves.C;
+      sa.LH = g_leaves.H;
+      sa.LL = g_leaves.L;
+      sa.leaf_cap = g_leaves.cap;
+    }
+    const int map = choose_mapping(d, n);
+    const int rg = rule_grid(map, n);
+    const int tg = tile_grid_for(n);
+    g_stats.lanes_per_region = map < 0 ? 1 : (1 << map);
+    if (timing) GM_HIP(hipEventRecord(ev[0], s));
+    GM_HIP(launch_rule(d, fam, map, ra, rg, s));
+    if (timing) GM_HIP(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, st, ra.partials, rg);
+    GM_HIP(hipGetLastError());
+    if (timing) GM_HIP(hipEventRecord(ev[2], s));
+    hipLaunchKernelGGL(classify_kernel, dim3(tg), dim3(kTileThreads), 0, s, ca);
+    GM_HIP(hipGetLastError());
+    if (timing) GM_HIP(hipEventRecord(ev[3], s));
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, st, ca.TK, sa.TOFF, ca.TQ, ca.TE);
+    GM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(scatter_kernel, dim3(tg), dim3(kTileThreads), 0, s, sa);
+    GM_HIP(hipGetLastError());
+    if (timing) GM_HIP(hipEventRecord(ev[4], s));
+    GM_HIP(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    if (timing) {
+      float a = 0, b = 0, c = 0, e = 0;
+      GM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+      GM_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+      GM_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
+      GM_HIP(hipEventElapsedTime(&e, ev[3], ev[4]));
+      g_stats.rule_ms += a;
+      g_stats.reduce_ms += b;
+      g_stats.classify_ms += c;
+      g_stats.split_ms += e;
+      g_stats.rule_launches += 1;
+    }
+    if (g_opt.log)
+      std::fprintf(stderr, "gm: iter %lld n %lld I %.17g E %.6g T %.6g done %lld\n",
+                   (long long)hst.iter, (long long)n, hst.I, hst.E, hst.T, (long long)hst.done);
+    leaves_have = hst.leaf_count;
+    if (hst.done) break;
+    n = hst.n_active;
+  }
+  if (timing)
+    for (auto& e : ev) (void)hipEventDestroy(e);
+
+  out->I = hst.I;
+  out->E = hst.E;
+  out->status = (int)hst.status;
+  out->final_n = hst.n_active;
+  out->buf = hst.buf;
+  out->leaf_count = keep_leaves ? hst.leaf_count : 0;
+  out->base = base;
+  out->lay = lay;
+  out->cap = cap;
+  out->vol_omega = vol;
+  g_stats.iterations = hst.iter;
+  g_stats.regions_evaluated = hst.regions_evaluated;
+  g_stats.evals = hst.regions_evaluated * gm_num_nodes(d);
+  g_stats.max_active = hst.max_active;
+  g_stats.final_active = hst.n_active;
+  g_stats.finished = hst.finished;
+  g_stats.status = hst.status;
+  g_stats.total_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  g_last.valid = true;
+  g_last.d = d;
+  g_last.n = hst.n_active;
+  g_last.cap = cap;
+  g_last.lay = lay;
+  g_last.buf = hst.buf;
+  return GM_OK;
+}
+
+}  // namespace gm
+
+using namespace gm;
+
+extern "C" {
+
+int64_t gm_num_nodes(int d) {
+  if (d < 1 || d > 62) return -1;
+  return ((int64_t)1 << d) + 2 * (int64_t)d * d + 2 * (int64_t)d + 1;
+}
+
+int gm_integrate(int integrand_id, const double* params, int d, const double* lo, const double* hi,
+                 double rel_tol, double abs_tol, int64_t max_regions, double* out_est,
+                 double* out_err, void* stream) {
+  int rc = validate(integrand_id, params, d, lo, hi, rel_tol, abs_tol);
+  if (rc != GM_OK) return rc;
+  if (!out_est || !out_err) return GM_EINVAL;
+  std::lock_guard<std::mutex> lk(api_mutex());
+  RunResult rr;
+  rc = run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions,
+                    (hipStream_t)stream, false, &rr);
+  if (rc != GM_OK) return rc;
+  *out_est = rr.I;
+  *out_err = rr.E;
+  return rr.status;
+}
+
+int gm_eval_regions(int integrand_id, const double* params, int d, const double* lo,
+                    const double* hi, int64_t n, const double* c, const double* h,
+                    const int32_t* lvl, double* out_q, double* out_err, int32_t* out_axis,
+                    void* stream) {
+  int rc = validate(integrand_id, params, d, lo, hi, 1.0, 1.0);
+  if (rc != GM_OK) return rc;
+  if (n < 0 || (n > 0 && (!c || !h || !lvl || !out_q || !out_err || !out_axis))) return GM_EINVAL;
+  for (int64_t r = 0; r < n; ++r)
+    if (lvl[r] < 0 || lvl[r] > 65535) return GM_EINVAL;
+  if (n == 0) return GM_OK;
+  std::lock_guard<std::mutex> lk(api_mutex());
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t cap = n;
+  const Layout lay = make_layout(d, cap);
+  char* base = nullptr;
+  rc = acquire_workspace(lay.total, &base);
+  if (rc != GM_OK) return rc;
+  g_last.valid = false;
+  std::vector<double> cs((size_t)d * n), hs((size_t)d * n);
+  std::vector<uint16_t> ls((size_t)n);
+  for (int64_t r = 0; r < n; ++r) {
+    for (int j = 0; j < d; ++j) {
+      cs[(size_t)j * n + r] = c[r * d + j];
+      hs[(size_t)j * n + r] = h[r * d + j];
+    }
+    ls[r] = (uint16_t)lvl[r];
+  }
+  RuleArgs ra;
+  std::memset(&ra, 0, sizeof ra);
+  fill_params(integrand_id, d, params, ra.P);
+  fill_consts(d, ra.K);
+  ra.C[0] = ra.C[1] = (const double*)(base + lay.C[0]);
+  ra.H[0] = ra.H[1] = (const double*)(base + lay.H[0]);
+  ra.L[0] = ra.L[1] = (const uint16_t*)(base + lay.L[0]);
+  ra.cap = cap;
+  ra.Q = (double*)(base + lay.Q);
+  ra.ERR = (double*)(base + lay.ERR);
+  ra.AXIS = (uint8_t*)(base + lay.AXIS);
+  ra.partials = (double*)(base + lay.PART);
+  ra.st = (Status*)(base + lay.ST);
+  double vol = 1.0;
+  for (int j = 0; j < d; ++j) vol = vol * (hi[j] - lo[j]);
+  ra.vol_omega = vol;
+  ra.n_fixed = n;
+  GM_HIP(hipMemcpyAsync((void*)ra.C[0], cs.data(), sizeof(double) * d * n, hipMemcpyHostToDevice, s));
+  GM_HIP(hipMemcpyAsync((void*)ra.H[0], hs.data(), sizeof(double) * d * n, hipMemcpyHostToDevice, s));
+  GM_HIP(hipMemcpyAsync((void*)ra.L[0], ls.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, s));
+  const int map = choose_mapping(d, n);
+  GM_HIP(launch_rule(d, integrand_id, map, ra, rule_grid(map, n), s));
+  std::vector<uint8_t> ax((size_t)n);
+  GM_HIP(hipMemcpyAsync(out_q, ra.Q, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  GM_HIP(hipMemcpyAsync(out_err, ra.ERR, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  GM_HIP(hipMemcpyAsync(ax.data(), ra.AXIS, n, hipMemcpyDeviceToHost, s));
+  GM_HIP(hipStreamSynchronize(s));
+  for (int64_t r = 0; r < n; ++r) out_axis[r] = ax[r];
+  return GM_OK;
+}
+
+int64_t gm_last_active(int64_t n, double* c, double* h, int32_t* lvl, double* q, double* err,
+                       int32_t* axis) {
+  std::lock_guard<std::mutex> lk(api_mutex());
+  if (!g_last.valid) return 0;
+  char* base = g_ext_ptr ? (char*)g_ext_ptr : (char*)g_own_ptr;
+  const int64_t cnt = std::min<int64_t>(n, g_last.n);
+  const int d = g_last.d;
+  const int b = g_last.buf;
+  const Layout& L = g_last.lay;
+  if (cnt <= 0) return g_last.n;
+  std::vector<double> buf((size_t)cnt);
+  for (int j = 0; j < d; ++j) {
+    if (c) {
+      if (hipMemcpy(buf.data(), base + L.C[b] + sizeof(double) * j * g_last.cap,
+                    sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+      for (int64_t r = 0; r < cnt; ++r) c[r * d + j] = buf[r];
+    }
+    if (h) {
+      if (hipMemcpy(buf.data(), base + L.H[b] + sizeof(double) * j * g_last.cap,
+                    sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
+        return -1;
+      for (int64_t r = 0; r < cnt; ++r) h[r * d + j] = buf[r];
+    }
+  }
+  if (lvl) {
+    std::vector<uint16_t> l((size_t)cnt);
+    if (hipMemcpy(l.data(), base + L.L[b], sizeof(uint16_t) * cnt, hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return -1;
+    for (int64_t r = 0; r < cnt; ++r) lvl[r] = l[r];
+  }
+  if (q && hipMemcpy(q, base + L.Q, sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
+    return -1;
+  if (err && hipMemcpy(err, base + L.ERR, sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
+    return -1;
+  if (axis) {
+    std::vector<uint8_t> a((size_t)cnt);
+    if (hipMemcpy(a.data(), base + L.AXIS, cnt, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    for (int64_t r = 0; r < cnt; ++r) axis[r] = a[r];
+  }
+  return g_last.n;
+}
+
+int gm_set_workspace(void* device_ptr, size_t bytes) {
+  std::lock_guard<std::mutex> lk(api_mutex());
+  g_last.valid = false;
+  if (!device_ptr || bytes == 0) {
+    g_ext_ptr = nullptr;
+    g_ext_bytes = 0;
+    return GM_OK;
+  }
+  g_ext_ptr = device_ptr;
+  g_ext_bytes = bytes;
+  return GM_OK;
+}
+
+size_t gm_workspace_bytes(int d, int64_t max_regions, int mode) {
+  if (d < kMinDim || d > kMaxDim || max_regions < 1) return 0;
+  if (mode == 2) return batch_layout_bytes(d, max_regions);
+  return make_layout(d, max_regions).total;
+}
+
+int gm_set_option(const char* key, int64_t value) {
+  if (!key) return GM_EINVAL;
+  std::lock_guard<std::mutex> lk(api_mutex());
+  const std::string k(key);
+  if (k == "init_log2_regions") {
+    if (value < 0 || value > 30) return GM_EINVAL;
+    g_opt.init_log2 = (int)value;
+  } else if (k == "max_iters") {
+    if (value < 1 || value > 1000000) return GM_EINVAL;
+    g_opt.max_iters = value;
+  } else if (k == "graph_iters") {
+    if (value < 0 || value > 64) return GM_EINVAL;
+    g_opt.graph_iters = (int)value;
+  } else if (k == "lanes_per_region") {
+    if (value < 0 || value > 64 || (value & (value - 1))) return GM_EINVAL;
+    g_opt.lanes_per_region = (int)value;
+  } else if (k == "timing") {
+    g_opt.timing = value ? 1 : 0;
+  } else if (k == "log") {
+    g_opt.log = value ? 1 : 0;
+  } else {
+    return GM_EINVAL;
+  }
+  return GM_OK;
+}
+
+const char* gm_status_string(int status) {
+  switch (status) {
+    case GM_OK: return "converged: E <= max(abs_tol, rel_tol*|I|)";
+    case GM_MAX_REGIONS: return "stopped: region capacity reached";
+    case GM_MAX_ITERS: return "stopped: iteration budget used up";
+    case GM_PRECISION_LIMIT: return "stopped: every region retired by a numerical guard, E > T";
+    case GM_NONFINITE: return "integrand or a rule sum was not finite";
+    case GM_EINVAL: return "invalid argument";
+    case GM_ENOMEM:
+      g_enomem_text = "out of device memory (or workspace too small); last HIP error: " + g_hip_err;
+      return g_enomem_text.c_str();
+    case GM_EHIP: return g_hip_err.c_str();
+    default: return "unknown status";
+  }
+}
+
+int gm_last_stats(gm_stats* out) {
+  if (!out) return GM_EINVAL;
+  std::lock_guard<std::mutex> lk(api_mutex());
+  *out = g_stats;
+  return GM_OK;
+}
+
+}  // extern "C"

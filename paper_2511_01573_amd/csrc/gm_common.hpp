@@ -1,0 +1,213 @@
+// gm_common.hpp -- device-side types shared by the libgm kernels (gfx950, FP64).
+//
+// Method: arXiv 2511.01573 (adaptive Genz-Malik cubature, Sec. 2-4).  This
+// header holds the kernel argument blocks, the device status block that drives
+// the iteration (Sec. 3 loop), compensated (double-double) summation and the
+// integrand definitions (Sec. 4 test functions and their Genz families).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gm {
+
+constexpr int kMaxDim = 16;
+constexpr int kMinDim = 2;
+
+// Integrand families (the numbering of include/gm.h).
+enum Family : int {
+  kOsc = 1,
+  kProductPeak = 2,
+  kCornerPeak = 3,
+  kGaussian = 4,
+  kC0 = 5,
+  kDiscontinuous = 6,
+  kPolyF7 = 7
+};
+
+// Integrand parameters as the kernels consume them.  a, u are the caller's;
+// inv_a2 = 1/(a*a) (product peak) and c0 = 2*pi*u_0 (oscillatory) are formed
+// once on the host with the same single roundings the definitions imply.
+struct DevParams {
+  double a[kMaxDim];
+  double u[kMaxDim];
+  double inv_a2[kMaxDim];
+  double c0;
+  int d;
+  int fam;
+};
+
+// Rule constants for one dimension d (Sec. 2; degree-7 fully symmetric rule
+// with generators 0, l2 e_i, l3 e_i, l4 (e_i +- e_j), l5 (+-1,...,+-1) and
+// its embedded degree-5 rule).  w = degree-7 weights, e = w - v (v the
+// degree-5 weights), r7 = l2^2 / l3^2 = 1/7.
+struct RuleConsts {
+  double lam2, lam3, lam4, lam5;
+  double w[5];
+  double e[5];
+  double r7;
+  double axis_band;  // relative noise band of the split-axis comparison
+};
+
+// Device status block: the only state the host reads between iterations.
+struct Status {
+  int64_t n_active;     // regions in the current active set
+  int64_t n_prev;       // active count of the iteration being split
+  int64_t n_keep;       // regions kept (to be split) this iteration
+  int64_t iter;         // evaluate steps done
+  int64_t done;         // 1 once a final status is set
+  int64_t status;       // GM_* code
+  int32_t nonfinite;    // set by the rule kernel
+  int32_t buf;          // ping-pong buffer that holds the active set
+  int64_t regions_evaluated;
+  int64_t finished;
+  int64_t max_active;
+  int64_t leaf_base;    // first leaf slot of this iteration's retired regions
+  int64_t leaf_count;   // retired leaves stored so far (gradient mode)
+  int64_t cap;          // active-set capacity
+  int64_t max_iters;
+  double I, E, T;
+  double ifin_hi, ifin_lo, efin_hi, efin_lo;
+  double rel_tol, abs_tol;
+  int64_t pad[4];
+};
+
+// ---------------------------------------------------------------------------
+// Compensated summation.  TwoSum (Knuth) is exact in binary64 as long as the
+// compiler does not reassociate; the library is built with -ffp-contract=off.
+// ---------------------------------------------------------------------------
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+
+__device__ __forceinline__ void dd_add(dd& x, double y) {
+  double s, e;
+  two_sum(x.hi, y, s, e);
+  x.hi = s;
+  x.lo += e;
+}
+
+__device__ __forceinline__ dd dd_sum(dd x, dd y) {
+  double s, e;
+  two_sum(x.hi, y.hi, s, e);
+  e += x.lo + y.lo;
+  dd r;
+  r.hi = s + e;
+  r.lo = e - (r.hi - s);
+  return r;
+}
+
+__device__ __forceinline__ double dd_val(dd x) { return x.hi + x.lo; }
+
+__device__ __forceinline__ dd shfl_xor_dd(dd v, int m) {
+  dd r;
+  r.hi = __shfl_xor(v.hi, m, 64);
+  r.lo = __shfl_xor(v.lo, m, 64);
+  return r;
+}
+
+// Sum of a double-double over the 64 lanes of a wavefront (butterfly; every
+// lane ends with the same value).
+__device__ __forceinline__ dd wave_sum_dd(dd v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = dd_sum(v, shfl_xor_dd(v, m));
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Integrands (Sec. 4).  The argument of every family is a left-to-right sum
+// over coordinates j = 0..d-1, exactly as written in the formulas; the
+// transcendental comes from the device math library.
+// ---------------------------------------------------------------------------
+template <int D, int FAM>
+__device__ __forceinline__ double integrand(const DevParams& P, const double (&x)[D]) {
+  if constexpr (FAM == kOsc) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) s = s + P.a[j] * x[j];
+    return cos(P.c0 + s);
+  } else if constexpr (FAM == kProductPeak) {
+    double den = 1.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double t = x[j] - P.u[j];
+      den = den * (P.inv_a2[j] + t * t);
+    }
+    return 1.0 / den;
+  } else if constexpr (FAM == kCornerPeak) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) s = s + P.a[j] * x[j];
+    return pow(1.0 + s, -(double)(D + 1));
+  } else if constexpr (FAM == kGaussian) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      double t = P.a[j] * (x[j] - P.u[j]);
+      s = s + t * t;
+    }
+    return exp(-s);
+  } else if constexpr (FAM == kC0) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) s = s + P.a[j] * fabs(x[j] - P.u[j]);
+    return exp(-s);
+  } else if constexpr (FAM == kDiscontinuous) {
+    bool out = false;
+#pragma unroll
+    for (int j = 0; j < D; ++j) out = out || (x[j] > P.u[j]);
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) s = s + P.a[j] * x[j];
+    return out ? 0.0 : exp(s);
+  } else {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) s = s + x[j] * x[j];
+    return pow(s, 11.0);
+  }
+}
+
+// Kernel arguments of the rule kernel (Sec. 2 evaluation of every region).
+struct RuleArgs {
+  DevParams P;
+  RuleConsts K;
+  const double* C[2];     // SoA centres  [j * cap + r], ping-pong
+  const double* H[2];     // SoA half-widths
+  const uint16_t* L[2];   // levels: region volume = vol_omega * 2^-lvl
+  int64_t cap;
+  double* Q;              // [cap] rule value
+  double* ERR;            // [cap] error estimate
+  uint8_t* AXIS;          // [cap] split axis, bit 7 = geometry guard
+  double* partials;       // [grid][4] double-double (Q, err) per block
+  Status* st;
+  double vol_omega;
+  int64_t n_fixed;        // >= 0: evaluate this many regions of buffer 0, ignore st
+};
+
+// One launcher per family (each built in its own translation unit).
+// log2l < 0: one lane per region (d <= kTprMaxDim); else 2^log2l lanes per
+// region (log2l in {2, 4, 6}, d >= 6, 8, 10 respectively).
+hipError_t launch_rule_f1(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+hipError_t launch_rule_f2(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+hipError_t launch_rule_f3(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+hipError_t launch_rule_f4(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+hipError_t launch_rule_f5(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+hipError_t launch_rule_f6(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+hipError_t launch_rule_f7(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+constexpr int kTprMaxDim = 10;
+constexpr int kRuleBlockSize = 256;
+
+}  // namespace gm

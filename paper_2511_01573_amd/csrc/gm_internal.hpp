@@ -1,0 +1,77 @@
+// gm_internal.hpp -- host-side declarations shared by the libgm translation
+// units (options, workspace layout, run results).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "gm_common.hpp"
+
+namespace gm {
+
+struct Options {
+  int init_log2 = 12;        // initial partition 2^(d*floor(init_log2/d)) cells
+  int64_t max_iters = 10000; // iteration budget
+  int graph_iters = 0;       // iterations per graph replay (0 = direct launches)
+  int lanes_per_region = 0;  // rule-kernel mapping (0 = automatic)
+  int timing = 0;            // per-phase hipEvent timing
+  int log = 0;               // per-iteration log to stderr
+};
+
+// Byte offsets of the device buffers of one run inside the workspace.
+struct Layout {
+  size_t C[2], H[2], L[2];
+  size_t Q, ERR, AXIS, FLAG;
+  size_t TK, TOFF, TQ, TE;
+  size_t PART, ST;
+  size_t total;
+};
+
+struct RunResult {
+  double I = 0, E = 0;
+  int status = 0;
+  int64_t final_n = 0;
+  int buf = 0;
+  int64_t leaf_count = 0;
+  char* base = nullptr;
+  Layout lay{};
+  int64_t cap = 0;
+  double vol_omega = 1.0;
+};
+
+Options& options();
+Layout make_layout(int d, int64_t cap);
+size_t align256(size_t x);
+int acquire_workspace(size_t bytes, char** base);
+void fill_consts(int d, RuleConsts& K);
+void fill_params(int fam, int d, const double* params, DevParams& P);
+int validate(int fam, const double* params, int d, const double* lo, const double* hi,
+             double rel_tol, double abs_tol);
+hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+// Rule-kernel mapping for n regions of dimension d: -1 = one lane per region,
+// else log2 of the lanes per region.
+int choose_mapping(int d, int64_t n);
+int rule_grid(int log2l, int64_t n);
+int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,
+                 double rel_tol, double abs_tol, int64_t max_regions, hipStream_t s,
+                 bool keep_leaves, RunResult* out);
+size_t batch_layout_bytes(int dmax, int64_t cap);
+
+// Process-wide lock serialising every C ABI call.
+std::mutex& api_mutex();
+// Record a HIP error for gm_status_string(GM_EHIP) and return GM_EHIP.
+int record_hip_error(hipError_t e);
+
+// The retired-leaf store of the last gradient-mode forward run (SoA).
+struct LeafView {
+  const double* C;
+  const double* H;
+  const uint16_t* L;
+  int64_t cap;
+};
+LeafView leaf_view();
+
+}  // namespace gm

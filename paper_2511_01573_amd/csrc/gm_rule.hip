@@ -1,0 +1,622 @@
+// gm_rule.hip -- the rule kernel: Genz-Malik rule, embedded-rule error
+// estimate and fourth-difference split axis on every active region
+// (arXiv 2511.01573, Sec. 2; the "evaluate subregions" step of Sec. 3).
+//
+// Node arithmetic.  Every integrand family is f(x) = G(T_0(x_0) (+) T_1(x_1)
+// (+) ... (+) T_{d-1}(x_{d-1})) with a per-coordinate term T_j, a left-to-
+// right combination (+) (a sum, or a product for the product peak) and an
+// outer function G.  A region's nodes take only seven values per coordinate
+// (c, c +- l2 h, c +- l3 h = c +- l4 h, c +- l5 h), so the terms are formed
+// once per region and every node's argument is a chain of (+) over those
+// terms in the same left-to-right order as the defining formula.  Common
+// prefixes of the chain are shared:
+//   - classes 1-4 (the centre, +-l2 e_i, +-l3 e_i, +-l4 (e_i +- e_j)) reuse
+//     the prefix of centre terms up to the first perturbed coordinate;
+//   - class 5 (the 2^d corners) is swept as a binary tree over the last four
+//     coordinates below an outer loop over the leading ones, so a corner
+//     costs about two (+) plus one G.
+//
+// Mappings.
+//   TPR (d <= 10): one lane per region, fully unrolled classes 1-4.
+//   WPR: L = 2^l lanes per region inside one wavefront.  Lane s fixes the
+//        signs of the first l coordinates of the corners it sweeps; the
+//        O(d^2) class 1-4 nodes are dealt out to the L lanes as work items
+//        (one axis: 4 nodes and its fourth difference; one axis pair: 4
+//        nodes) using per-region term tables in LDS.  Class sums are combined
+//        across the L lanes with shuffles.
+// Class sums are compensated (TwoSum per 16 corners or per node).
+#include "gm_common.hpp"
+
+namespace gm {
+
+constexpr int kRuleBlock = kRuleBlockSize;
+
+// ---------------------------------------------------------------------------
+// Family traits: term, combination and outer function (Sec. 4 integrands).
+// ---------------------------------------------------------------------------
+template <int FAM>
+struct Fam {
+  static constexpr bool kProduct = (FAM == kProductPeak);
+  __device__ static __forceinline__ double term(const DevParams& P, int j, double x) {
+    if constexpr (FAM == kOsc || FAM == kCornerPeak) {
+      return P.a[j] * x;
+    } else if constexpr (FAM == kProductPeak) {
+      const double t = x - P.u[j];
+      return P.inv_a2[j] + t * t;
+    } else if constexpr (FAM == kGaussian) {
+      const double t = P.a[j] * (x - P.u[j]);
+      return t * t;
+    } else if constexpr (FAM == kC0) {
+      return P.a[j] * fabs(x - P.u[j]);
+    } else if constexpr (FAM == kDiscontinuous) {
+      // outside the box x_j <= u_j the sum becomes -inf and G gives 0
+      return (x > P.u[j]) ? -__builtin_inf() : P.a[j] * x;
+    } else {
+      return x * x;
+    }
+  }
+  __device__ static __forceinline__ double comb(double s, double t) {
+    if constexpr (kProduct) return s * t;
+    else return s + t;
+  }
+  template <int D>
+  __device__ static __forceinline__ double outer(const DevParams& P, double s) {
+    if constexpr (FAM == kOsc) {
+      return cos(P.c0 + s);
+    } else if constexpr (FAM == kProductPeak) {
+      return 1.0 / s;
+    } else if constexpr (FAM == kCornerPeak) {
+      // (1 + s)^-(d+1): binary powering, then one correctly rounded division
+      const double b = 1.0 + s;
+      double y = 1.0, p = b;
+      int e = D + 1;
+      bool first = true;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        if (e & 1) {
+          y = first ? p : y * p;
+          first = false;
+        }
+        e >>= 1;
+        if (e) p = p * p;
+      }
+      return 1.0 / y;
+    } else if constexpr (FAM == kGaussian || FAM == kC0) {
+      return exp(-s);
+    } else if constexpr (FAM == kDiscontinuous) {
+      return exp(s);
+    } else {
+      const double s2 = s * s;
+      const double s4 = s2 * s2;
+      const double s8 = s4 * s4;
+      return (s8 * s2) * s;
+    }
+  }
+};
+
+struct KSum {
+  double s, c;
+};
+__device__ __forceinline__ void ks_add(KSum& k, double x) {
+  double t, e;
+  two_sum(k.s, x, t, e);
+  k.s = t;
+  k.c += e;
+}
+__device__ __forceinline__ double ks_val(const KSum& k) { return k.s + k.c; }
+__device__ __forceinline__ KSum ks_merge(KSum a, KSum b) {
+  double t, e;
+  two_sum(a.s, b.s, t, e);
+  a.s = t;
+  a.c += e + b.c;
+  return a;
+}
+__device__ __forceinline__ KSum shfl_xor_ks(KSum v, int m) {
+  KSum r;
+  r.s = __shfl_xor(v.s, m, 64);
+  r.c = __shfl_xor(v.c, m, 64);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Corner sweep: binary tree over coordinates D-U .. D-1 below a prefix.
+// ---------------------------------------------------------------------------
+template <int D, int FAM, int U, int K, bool HAS_PREFIX>
+__device__ __forceinline__ void corner_tree(const DevParams& P, double s, const double (&t5p)[D],
+                                            const double (&t5m)[D], double& local) {
+  if constexpr (K == U) {
+    local += Fam<FAM>::template outer<D>(P, s);
+  } else {
+    constexpr int j = D - U + K;
+    if constexpr (!HAS_PREFIX && K == 0) {
+      corner_tree<D, FAM, U, K + 1, true>(P, t5p[j], t5p, t5m, local);
+      corner_tree<D, FAM, U, K + 1, true>(P, t5m[j], t5p, t5m, local);
+    } else {
+      corner_tree<D, FAM, U, K + 1, true>(P, Fam<FAM>::comb(s, t5p[j]), t5p, t5m, local);
+      corner_tree<D, FAM, U, K + 1, true>(P, Fam<FAM>::comb(s, t5m[j]), t5p, t5m, local);
+    }
+  }
+}
+
+// Sweep the corners whose first LB coordinates have the signs given by
+// `lane_bits` (bit j set -> -l5), i.e. 2^(D - LB) corners, into S5.
+template <int D, int FAM, int LB>
+__device__ __forceinline__ void corner_sweep(const DevParams& P, const double (&t5p)[D],
+                                             const double (&t5m)[D], uint32_t lane_bits, KSum& S5) {
+  constexpr int U = (D - LB) < 4 ? (D - LB) : 4;  // inner tree depth
+  constexpr int NOUT = D - LB - U;                 // looped coordinates
+  // lane prefix over coordinates 0 .. LB-1
+  double pl = 0.0;
+#pragma unroll
+  for (int j = 0; j < LB; ++j) {
+    const double t = ((lane_bits >> j) & 1u) ? t5m[j] : t5p[j];
+    pl = (j == 0) ? t : Fam<FAM>::comb(pl, t);
+  }
+  for (uint32_t m = 0; m < (1u << NOUT); ++m) {
+    double pre = pl;
+#pragma unroll
+    for (int q = 0; q < NOUT; ++q) {
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int j = LB + q;
+      const double t = ((m >> q) & 1u) ? t5m[j] : t5p[j];
+      pre = (LB == 0 && q == 0) ? t : Fam<FAM>::comb(pre, t);
+    }
+    double local = 0.0;
+    corner_tree<D, FAM, U, 0, (LB + NOUT) != 0>(P, pre, t5p, t5m, local);
+    ks_add(S5, local);
+  }
+}
+
+struct RegionResult {
+  double q, err;
+  int axis;
+  int geo;
+  int nonfinite;
+};
+
+__device__ __forceinline__ void rule_combine(const RuleConsts& K, double s1, double s2, double s3,
+                                             double s4, double s5, double vol, RegionResult& r) {
+  r.nonfinite = !(isfinite(s1) && isfinite(s2) && isfinite(s3) && isfinite(s4) && isfinite(s5));
+  double q = K.w[0] * s1 + K.w[1] * s2;
+  q = q + K.w[2] * s3;
+  q = q + K.w[3] * s4;
+  q = q + K.w[4] * s5;
+  double er = K.e[0] * s1 + K.e[1] * s2;
+  er = er + K.e[2] * s3;
+  er = er + K.e[3] * s4;
+  er = er + K.e[4] * s5;
+  r.q = vol * q;
+  r.err = vol * fabs(er);
+}
+
+// Fourth difference of axis i and the magnitude of the terms it cancels.
+__device__ __forceinline__ void fourth_diff(const RuleConsts& K, double f0, double fp2, double fm2,
+                                            double fp3, double fm3, double& Dv, double& sc) {
+  const double A = (fp2 + fm2) - 2.0 * f0;
+  const double B = (fp3 + fm3) - 2.0 * f0;
+  Dv = fabs(A - B * K.r7);
+  sc = (fabs(fp2) + fabs(fm2) + 2.0 * fabs(f0)) + K.r7 * (fabs(fp3) + fabs(fm3) + 2.0 * fabs(f0));
+}
+
+__device__ __forceinline__ void store_result(const RuleArgs& A, int64_t r, const RegionResult& o) {
+  A.Q[r] = o.q;
+  A.ERR[r] = o.err;
+  A.AXIS[r] = (uint8_t)(o.axis | (o.geo << 7));
+}
+
+__device__ __forceinline__ void block_partials(const RuleArgs& A, dd qs, dd es, int nonfin) {
+  __shared__ dd sq[kRuleBlock / 64], se[kRuleBlock / 64];
+  __shared__ int snf[kRuleBlock / 64];
+  qs = wave_sum_dd(qs);
+  es = wave_sum_dd(es);
+  const int anynf = __any(nonfin);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sq[w] = qs;
+    se[w] = es;
+    snf[w] = anynf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd tq = sq[0], te = se[0];
+    int nf = snf[0];
+    for (int k = 1; k < kRuleBlock / 64; ++k) {
+      tq = dd_sum(tq, sq[k]);
+      te = dd_sum(te, se[k]);
+      nf |= snf[k];
+    }
+    double* p = A.partials + 4 * (int64_t)blockIdx.x;
+    p[0] = tq.hi;
+    p[1] = tq.lo;
+    p[2] = te.hi;
+    p[3] = te.lo;
+    if (nf && A.n_fixed < 0) atomicOr(&A.st->nonfinite, 1);
+  }
+}
+
+__device__ __forceinline__ bool active_range(const RuleArgs& A, int64_t& n, int& buf) {
+  if (A.n_fixed >= 0) {
+    n = A.n_fixed;
+    buf = 0;
+    return true;
+  }
+  if (A.st->done) return false;
+  n = A.st->n_active;
+  buf = A.st->buf;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// TPR: one lane per region (d <= 10).
+// ---------------------------------------------------------------------------
+template <int D, int FAM>
+__device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, const RuleConsts& K,
+                                                        const double (&c)[D], const double (&h)[D],
+                                                        double vol) {
+  using F = Fam<FAM>;
+  double tc[D], t2p[D], t2m[D], t3p[D], t3m[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    tc[j] = F::term(P, j, c[j]);
+    t2p[j] = F::term(P, j, fma(K.lam2, h[j], c[j]));
+    t2m[j] = F::term(P, j, fma(-K.lam2, h[j], c[j]));
+    t3p[j] = F::term(P, j, fma(K.lam3, h[j], c[j]));
+    t3m[j] = F::term(P, j, fma(-K.lam3, h[j], c[j]));
+  }
+  // pc[k] = tc[0] (+) ... (+) tc[k-1]
+  double pc[D + 1];
+  pc[0] = 0.0;
+  pc[1] = tc[0];
+#pragma unroll
+  for (int k = 2; k <= D; ++k) pc[k] = F::comb(pc[k - 1], tc[k - 1]);
+  const double f0 = F::template outer<D>(P, pc[D]);
+  KSum S2 = {0.0, 0.0}, S3 = {0.0, 0.0}, S4 = {0.0, 0.0}, S5 = {0.0, 0.0};
+  double Dv[D], sc[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double v[4] = {t2p[i], t2m[i], t3p[i], t3m[i]};
+    double f[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double s = (i == 0) ? v[q] : F::comb(pc[i], v[q]);
+#pragma unroll
+      for (int k = i + 1; k < D; ++k) s = F::comb(s, tc[k]);
+      f[q] = F::template outer<D>(P, s);
+    }
+    ks_add(S2, f[0]);
+    ks_add(S2, f[1]);
+    ks_add(S3, f[2]);
+    ks_add(S3, f[3]);
+    fourth_diff(K, f0, f[0], f[1], f[2], f[3], Dv[i], sc[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < D - 1; ++i) {
+#pragma unroll
+    for (int si = 0; si < 2; ++si) {
+      const double ti = si ? t3m[i] : t3p[i];
+      double m = (i == 0) ? ti : F::comb(pc[i], ti);
+#pragma unroll
+      for (int j = i + 1; j < D; ++j) {
+#pragma unroll
+        for (int sj = 0; sj < 2; ++sj) {
+          double s = F::comb(m, sj ? t3m[j] : t3p[j]);
+#pragma unroll
+          for (int k = j + 1; k < D; ++k) s = F::comb(s, tc[k]);
+          ks_add(S4, F::template outer<D>(P, s));
+        }
+        m = F::comb(m, tc[j]);
+      }
+    }
+  }
+  double t5p[D], t5m[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    t5p[j] = F::term(P, j, fma(K.lam5, h[j], c[j]));
+    t5m[j] = F::term(P, j, fma(-K.lam5, h[j], c[j]));
+  }
+  corner_sweep<D, FAM, 0>(P, t5p, t5m, 0u, S5);
+
+  RegionResult r;
+  rule_combine(K, f0, ks_val(S2), ks_val(S3), ks_val(S4), ks_val(S5), vol, r);
+  double dmax = -1.0, scale = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    dmax = Dv[i] > dmax ? Dv[i] : dmax;
+    scale = sc[i] > scale ? sc[i] : scale;
+  }
+  const double thr = dmax - K.axis_band * scale;
+  int axis = -1;
+  double hb = 0.0, cb = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    if (Dv[i] >= thr && (axis < 0 || h[i] > hb)) {
+      axis = i;
+      hb = h[i];
+      cb = c[i];
+    }
+  }
+  if (axis < 0) {
+    axis = 0;
+    hb = h[0];
+    cb = c[0];
+  }
+  const double hp = hb * 0.5;
+  r.axis = axis;
+  r.geo = (cb - hp == cb) || (cb + hp == cb) || (hp == 0.0);
+  return r;
+}
+
+template <int D, int FAM>
+__global__ __launch_bounds__(kRuleBlock) void rule_tpr_kernel(RuleArgs A) {
+  int64_t n;
+  int buf;
+  if (!active_range(A, n, buf)) return;
+  const double* __restrict__ Cb = A.C[buf];
+  const double* __restrict__ Hb = A.H[buf];
+  const uint16_t* __restrict__ Lb = A.L[buf];
+  const int64_t cap = A.cap;
+  dd qs = {0.0, 0.0}, es = {0.0, 0.0};
+  int nonfin = 0;
+  for (int64_t r = (int64_t)blockIdx.x * kRuleBlock + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * kRuleBlock) {
+    double c[D], h[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      c[j] = Cb[j * cap + r];
+      h[j] = Hb[j * cap + r];
+    }
+    const double vol = ldexp(A.vol_omega, -(int)Lb[r]);
+    const RegionResult o = rule_region_tpr<D, FAM>(A.P, A.K, c, h, vol);
+    store_result(A, r, o);
+    dd_add(qs, o.q);
+    dd_add(es, o.err);
+    nonfin |= o.nonfinite;
+  }
+  block_partials(A, qs, es, nonfin);
+}
+
+// ---------------------------------------------------------------------------
+// WPR: L = 2^LOG2L lanes per region.
+// ---------------------------------------------------------------------------
+// LDS per region: c[D], h[D], tc[D], pc[D] (pc[k] = tc[0] (+) .. (+) tc[k-1]),
+// D_i[D], scale_i[D].
+template <int D>
+struct WprSlot {
+  double c[D], h[D], tc[D], pc[D], dv[D], sc[D];
+};
+
+// The (i, j) pair with lexicographic index p, i < j < D.
+template <int D>
+__device__ __forceinline__ void pair_of(int p, int& i, int& j) {
+  i = 0;
+  int row = D - 1;
+  while (p >= row) {
+    p -= row;
+    ++i;
+    --row;
+  }
+  j = i + 1 + p;
+}
+
+template <int D, int FAM>
+__device__ __forceinline__ double chain_tail(double s, const double* tc, int k0) {
+  for (int k = k0; k < D; ++k) s = Fam<FAM>::comb(s, tc[k]);
+  return s;
+}
+
+template <int D, int FAM, int LOG2L>
+__global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
+  using F = Fam<FAM>;
+  constexpr int L = 1 << LOG2L;
+  constexpr int RPB = kRuleBlock / L;  // regions per block step
+  constexpr int NPAIR = D * (D - 1) / 2;
+  constexpr int NITEM = D + NPAIR;
+  __shared__ WprSlot<D> slots[RPB];
+  int64_t n;
+  int buf;
+  if (!active_range(A, n, buf)) return;
+  const double* __restrict__ Cb = A.C[buf];
+  const double* __restrict__ Hb = A.H[buf];
+  const uint16_t* __restrict__ Lb = A.L[buf];
+  const int64_t cap = A.cap;
+  const RuleConsts& K = A.K;
+  const DevParams& P = A.P;
+  const int g = threadIdx.x >> LOG2L;  // region slot in the block
+  const int s = threadIdx.x & (L - 1);
+  WprSlot<D>& sl = slots[g];
+  dd qs = {0.0, 0.0}, es = {0.0, 0.0};
+  int nonfin = 0;
+  for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
+    const int64_t r = base + g;
+    const bool valid = r < n;
+    double c[D], h[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      c[j] = valid ? Cb[j * cap + r] : 0.5;
+      h[j] = valid ? Hb[j * cap + r] : 0.25;
+    }
+    // Per-region tables (each lane of the group writes the coordinates j = s mod L).
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if ((j & (L - 1)) == s) {
+        sl.c[j] = c[j];
+        sl.h[j] = h[j];
+      }
+    }
+    double tc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) tc[j] = F::term(P, j, c[j]);
+    double pc = 0.0, full = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if ((k & (L - 1)) == s) {
+        sl.tc[k] = tc[k];
+        sl.pc[k] = pc;
+      }
+      pc = (k == 0) ? tc[0] : F::comb(pc, tc[k]);
+    }
+    full = pc;
+    __syncthreads();
+    const double f0 = F::template outer<D>(P, full);
+    KSum S2 = {0.0, 0.0}, S3 = {0.0, 0.0}, S4 = {0.0, 0.0}, S5 = {0.0, 0.0};
+    // Classes 2-4 as work items.
+    for (int it = s; it < NITEM; it += L) {
+      if (it < D) {
+        const int i = it;
+        const double ci = sl.c[i], hi = sl.h[i];
+        const double v[4] = {F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci)),
+                             F::term(P, i, fma(K.lam3, hi, ci)), F::term(P, i, fma(-K.lam3, hi, ci))};
+        double f[4];
+        const double pci = sl.pc[i];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double s0 = (i == 0) ? v[q] : F::comb(pci, v[q]);
+          f[q] = F::template outer<D>(P, chain_tail<D, FAM>(s0, sl.tc, i + 1));
+        }
+        ks_add(S2, f[0]);
+        ks_add(S2, f[1]);
+        ks_add(S3, f[2]);
+        ks_add(S3, f[3]);
+        double dv, scv;
+        fourth_diff(K, f0, f[0], f[1], f[2], f[3], dv, scv);
+        sl.dv[i] = dv;
+        sl.sc[i] = scv;
+      } else {
+        int i, j;
+        pair_of<D>(it - D, i, j);
+        const double ci = sl.c[i], hi = sl.h[i], cj = sl.c[j], hj = sl.h[j];
+        const double tj[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
+        const double pci = sl.pc[i];
+#pragma unroll
+        for (int si = 0; si < 2; ++si) {
+          const double ti = F::term(P, i, fma(si ? -K.lam4 : K.lam4, hi, ci));
+          double m = (i == 0) ? ti : F::comb(pci, ti);
+          for (int k = i + 1; k < j; ++k) m = F::comb(m, sl.tc[k]);
+#pragma unroll
+          for (int sj = 0; sj < 2; ++sj)
+            ks_add(S4, F::template outer<D>(P, chain_tail<D, FAM>(F::comb(m, tj[sj]), sl.tc, j + 1)));
+        }
+      }
+    }
+    // Class 5: this lane's 2^(D - LOG2L) corners.
+    {
+      double t5p[D], t5m[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        t5p[j] = F::term(P, j, fma(K.lam5, h[j], c[j]));
+        t5m[j] = F::term(P, j, fma(-K.lam5, h[j], c[j]));
+      }
+      corner_sweep<D, FAM, LOG2L>(P, t5p, t5m, (uint32_t)s, S5);
+    }
+    // Combine the L lanes of the group.
+#pragma unroll
+    for (int m = L / 2; m >= 1; m >>= 1) {
+      S2 = ks_merge(S2, shfl_xor_ks(S2, m));
+      S3 = ks_merge(S3, shfl_xor_ks(S3, m));
+      S4 = ks_merge(S4, shfl_xor_ks(S4, m));
+      S5 = ks_merge(S5, shfl_xor_ks(S5, m));
+    }
+    __syncthreads();
+    RegionResult o;
+    o.q = 0.0;
+    o.err = 0.0;
+    o.nonfinite = 0;
+    if (s == 0 && valid) {
+      const double vol = ldexp(A.vol_omega, -(int)Lb[r]);
+      rule_combine(K, f0, ks_val(S2), ks_val(S3), ks_val(S4), ks_val(S5), vol, o);
+      double dmax = -1.0, scale = 0.0;
+      for (int i = 0; i < D; ++i) {
+        dmax = sl.dv[i] > dmax ? sl.dv[i] : dmax;
+        scale = sl.sc[i] > scale ? sl.sc[i] : scale;
+      }
+      const double thr = dmax - K.axis_band * scale;
+      int axis = -1;
+      double hb = 0.0, cb = 0.0;
+      for (int i = 0; i < D; ++i) {
+        if (sl.dv[i] >= thr && (axis < 0 || sl.h[i] > hb)) {
+          axis = i;
+          hb = sl.h[i];
+          cb = sl.c[i];
+        }
+      }
+      if (axis < 0) {
+        axis = 0;
+        hb = sl.h[0];
+        cb = sl.c[0];
+      }
+      const double hp = hb * 0.5;
+      o.axis = axis;
+      o.geo = (cb - hp == cb) || (cb + hp == cb) || (hp == 0.0);
+      store_result(A, r, o);
+      dd_add(qs, o.q);
+      dd_add(es, o.err);
+      nonfin |= o.nonfinite;
+    }
+    __syncthreads();
+  }
+  block_partials(A, qs, es, nonfin);
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch over (d, mapping) for the family this translation unit is built
+// for (-DGM_RULE_FAMILY=k; the build compiles one object per family).
+// ---------------------------------------------------------------------------
+#ifndef GM_RULE_FAMILY
+#error "compile with -DGM_RULE_FAMILY=<1..7>"
+#endif
+
+using RuleFn = void (*)(RuleArgs);
+
+template <int D>
+static RuleFn pick(int log2l) {
+  constexpr int F = GM_RULE_FAMILY;
+  if (log2l < 0) {
+    if constexpr (D <= kTprMaxDim) return rule_tpr_kernel<D, F>;
+    return nullptr;
+  }
+  if constexpr (D >= 6) {
+    if (log2l == 2) return rule_wpr_kernel<D, F, 2>;
+    if constexpr (D >= 8) {
+      if (log2l == 4) return rule_wpr_kernel<D, F, 4>;
+    }
+    if constexpr (D >= 10) {
+      if (log2l == 6) return rule_wpr_kernel<D, F, 6>;
+    }
+  }
+  return nullptr;
+}
+
+static RuleFn rule_fn(int d, int log2l) {
+  switch (d) {
+    case 2: return pick<2>(log2l);
+    case 3: return pick<3>(log2l);
+    case 4: return pick<4>(log2l);
+    case 5: return pick<5>(log2l);
+    case 6: return pick<6>(log2l);
+    case 7: return pick<7>(log2l);
+    case 8: return pick<8>(log2l);
+    case 9: return pick<9>(log2l);
+    case 10: return pick<10>(log2l);
+    case 11: return pick<11>(log2l);
+    case 12: return pick<12>(log2l);
+    case 13: return pick<13>(log2l);
+    case 14: return pick<14>(log2l);
+    case 15: return pick<15>(log2l);
+    case 16: return pick<16>(log2l);
+    default: return nullptr;
+  }
+}
+
+#define GM_CAT2(a, b) a##b
+#define GM_CAT(a, b) GM_CAT2(a, b)
+
+hipError_t GM_CAT(launch_rule_f, GM_RULE_FAMILY)(int d, int log2l, const RuleArgs& a, int grid,
+                                                 hipStream_t s) {
+  RuleFn fn = rule_fn(d, log2l);
+  if (!fn) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kRuleBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace gm
