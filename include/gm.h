@@ -89,7 +89,8 @@ int gm_integrate(int integrand_id, const double* params, int d, const double* lo
 /*
  * gm_integrate_batch -- n independent integrals in one lock-stepped,
  * device-resident region store (thousands of small integrals at once).
- *   integrand_ids int[n]; d int[n] (2..16)
+ *   integrand_ids int[n]; d int[n] (2..16 for the packing; items with d > 10
+ *                 are rejected with GM_EINVAL in out_status)
  *   params        packed: item i contributes 2*d[i] doubles (a then u)
  *   lo, hi        packed: item i contributes d[i] doubles each
  *   rel_tol, abs_tol double[n]
@@ -142,7 +143,8 @@ int gm_eval_regions(int integrand_id, const double* params, int d, const double*
 int gm_set_workspace(void* device_ptr, size_t bytes);
 
 /* Bytes of device workspace one call needs: mode 0 integrate, 1 grad (without
-   the leaf store, which grows on demand), 2 batch (d = max item dimension). */
+   the leaf store, which grows on demand), 2 batch (d = max item dimension,
+   max_regions = max_regions_total, up to 65536 items). */
 size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
 
 /*
@@ -179,6 +181,16 @@ typedef struct {
 } gm_stats;
 
 int gm_last_stats(gm_stats* out);
+
+/*
+ * gm_set_tile -- tile shape the batched rule kernels use for items of
+ * dimension d (2..10) and family integrand_id: lanes_per_region 1 (one lane
+ * per region) or 4/16/64 (lanes of one wavefront sharing a region's corner
+ * sweep; needs d >= 6/8/10), grid_blocks = workgroups of 256 lanes launched
+ * (grid-stride; 0 = default 2048).  lanes_per_region = 0 removes the entry.
+ * Written by the project's autotuner (paper_2511_01573_amd/autotune.py).
+ */
+int gm_set_tile(int d, int integrand_id, int lanes_per_region, int grid_blocks);
 
 /* Number of integrand nodes per region, 2^d + 2 d^2 + 2 d + 1. */
 int64_t gm_num_nodes(int d);

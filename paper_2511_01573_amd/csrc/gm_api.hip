@@ -410,6 +410,9 @@ std::mutex& api_mutex() {
 
 int record_hip_error(hipError_t e) { return hip_fail(e); }
 
+void stats_reset() { std::memset(&g_stats, 0, sizeof g_stats); }
+gm_stats& stats_ref() { return g_stats; }
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 Layout make_layout(int d, int64_t cap) {
@@ -515,20 +518,27 @@ int validate(int fam, const double* params, int d, const double* lo, const doubl
 
 int init_cells_log2(int d) { return g_opt.init_log2 / d; }
 
-hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s) {
+RuleKernelFn rule_kernel(int d, int fam, int log2l, bool batch) {
   switch (fam) {
-    case 1: return launch_rule_f1(d, log2l, a, grid, s);
-    case 2: return launch_rule_f2(d, log2l, a, grid, s);
-    case 3: return launch_rule_f3(d, log2l, a, grid, s);
-    case 4: return launch_rule_f4(d, log2l, a, grid, s);
-    case 5: return launch_rule_f5(d, log2l, a, grid, s);
-    case 6: return launch_rule_f6(d, log2l, a, grid, s);
-    case 7: return launch_rule_f7(d, log2l, a, grid, s);
-    default: return hipErrorInvalidValue;
+    case 1: return rule_kernel_f1(d, log2l, batch);
+    case 2: return rule_kernel_f2(d, log2l, batch);
+    case 3: return rule_kernel_f3(d, log2l, batch);
+    case 4: return rule_kernel_f4(d, log2l, batch);
+    case 5: return rule_kernel_f5(d, log2l, batch);
+    case 6: return rule_kernel_f6(d, log2l, batch);
+    case 7: return rule_kernel_f7(d, log2l, batch);
+    default: return nullptr;
   }
 }
 
-static bool mapping_allowed(int d, int log2l) {
+hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s) {
+  RuleKernelFn fn = rule_kernel(d, fam, log2l, false);
+  if (!fn) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kRuleBlockSize), 0, s, a);
+  return hipGetLastError();
+}
+
+bool mapping_allowed(int d, int log2l) {
   if (log2l < 0) return d <= kTprMaxDim;
   if (log2l == 2) return d >= 6;
   if (log2l == 4) return d >= 8;

@@ -195,18 +195,33 @@ struct RuleArgs {
   Status* st;
   double vol_omega;
   int64_t n_fixed;        // >= 0: evaluate this many regions of buffer 0, ignore st
+  // Batch mode (the BATCH kernels): regions [grp[0], grp[1]) of one (d, family)
+  // group of a batch store; region r belongs to item IT[buf][r] with parameters
+  // PARAMS[item] and domain volume VOL[item]; buf = *bbuf.
+  const uint32_t* IT[2];
+  const DevParams* PARAMS;
+  const double* VOL;
+  const int64_t* grp;
+  const int32_t* bbuf;
 };
+
+// AXIS byte: bits 0-5 split axis, bit 6 non-finite rule sums, bit 7 geometry guard.
+constexpr uint8_t kAxisMask = 0x3f;
+constexpr uint8_t kNonfiniteBit = 0x40;
+constexpr uint8_t kGeoBit = 0x80;
 
 // One launcher per family (each built in its own translation unit).
 // log2l < 0: one lane per region (d <= kTprMaxDim); else 2^log2l lanes per
 // region (log2l in {2, 4, 6}, d >= 6, 8, 10 respectively).
-hipError_t launch_rule_f1(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
-hipError_t launch_rule_f2(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
-hipError_t launch_rule_f3(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
-hipError_t launch_rule_f4(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
-hipError_t launch_rule_f5(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
-hipError_t launch_rule_f6(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
-hipError_t launch_rule_f7(int d, int log2l, const RuleArgs& a, int grid, hipStream_t s);
+// batch = true selects the batch-store kernels (per-region item parameters).
+using RuleKernelFn = void (*)(RuleArgs);
+RuleKernelFn rule_kernel_f1(int d, int log2l, bool batch);
+RuleKernelFn rule_kernel_f2(int d, int log2l, bool batch);
+RuleKernelFn rule_kernel_f3(int d, int log2l, bool batch);
+RuleKernelFn rule_kernel_f4(int d, int log2l, bool batch);
+RuleKernelFn rule_kernel_f5(int d, int log2l, bool batch);
+RuleKernelFn rule_kernel_f6(int d, int log2l, bool batch);
+RuleKernelFn rule_kernel_f7(int d, int log2l, bool batch);
 constexpr int kTprMaxDim = 10;
 constexpr int kRuleBlockSize = 256;
 

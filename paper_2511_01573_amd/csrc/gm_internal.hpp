@@ -8,6 +8,7 @@
 
 #include <mutex>
 
+#include "../../include/gm.h"
 #include "gm_common.hpp"
 
 namespace gm {
@@ -54,6 +55,8 @@ hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, h
 // Rule-kernel mapping for n regions of dimension d: -1 = one lane per region,
 // else log2 of the lanes per region.
 int choose_mapping(int d, int64_t n);
+RuleKernelFn rule_kernel(int d, int fam, int log2l, bool batch);
+bool mapping_allowed(int d, int log2l);
 int rule_grid(int log2l, int64_t n);
 int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,
                  double rel_tol, double abs_tol, int64_t max_regions, hipStream_t s,
@@ -73,5 +76,9 @@ struct LeafView {
   int64_t cap;
 };
 LeafView leaf_view();
+
+// Statistics of the last call (gm_last_stats).
+void stats_reset();
+gm_stats& stats_ref();
 
 }  // namespace gm

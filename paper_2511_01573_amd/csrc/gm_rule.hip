@@ -202,7 +202,7 @@ __device__ __forceinline__ void fourth_diff(const RuleConsts& K, double f0, doub
 __device__ __forceinline__ void store_result(const RuleArgs& A, int64_t r, const RegionResult& o) {
   A.Q[r] = o.q;
   A.ERR[r] = o.err;
-  A.AXIS[r] = (uint8_t)(o.axis | (o.geo << 7));
+  A.AXIS[r] = (uint8_t)(o.axis | (o.nonfinite ? kNonfiniteBit : 0) | (o.geo ? kGeoBit : 0));
 }
 
 __device__ __forceinline__ void block_partials(const RuleArgs& A, dd qs, dd es, int nonfin) {
@@ -235,16 +235,39 @@ __device__ __forceinline__ void block_partials(const RuleArgs& A, dd qs, dd es, 
   }
 }
 
-__device__ __forceinline__ bool active_range(const RuleArgs& A, int64_t& n, int& buf) {
+// Regions [start, end) of the store buffer `buf` this launch evaluates.
+template <bool BATCH>
+__device__ __forceinline__ bool active_range(const RuleArgs& A, int64_t& start, int64_t& end,
+                                             int& buf) {
+  if constexpr (BATCH) {
+    start = A.grp[0];
+    end = A.grp[1];
+    buf = *A.bbuf;
+    return end > start;
+  }
+  start = 0;
   if (A.n_fixed >= 0) {
-    n = A.n_fixed;
+    end = A.n_fixed;
     buf = 0;
     return true;
   }
   if (A.st->done) return false;
-  n = A.st->n_active;
+  end = A.st->n_active;
   buf = A.st->buf;
   return true;
+}
+
+template <bool BATCH>
+__device__ __forceinline__ const DevParams& region_params(const RuleArgs& A, int buf, int64_t r,
+                                                         double& vol_omega) {
+  if constexpr (BATCH) {
+    const uint32_t item = A.IT[buf][r];
+    vol_omega = A.VOL[item];
+    return A.PARAMS[item];
+  } else {
+    vol_omega = A.vol_omega;
+    return A.P;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -347,18 +370,18 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
   return r;
 }
 
-template <int D, int FAM>
+template <int D, int FAM, bool BATCH>
 __global__ __launch_bounds__(kRuleBlock) void rule_tpr_kernel(RuleArgs A) {
-  int64_t n;
+  int64_t start, end;
   int buf;
-  if (!active_range(A, n, buf)) return;
+  if (!active_range<BATCH>(A, start, end, buf)) return;
   const double* __restrict__ Cb = A.C[buf];
   const double* __restrict__ Hb = A.H[buf];
   const uint16_t* __restrict__ Lb = A.L[buf];
   const int64_t cap = A.cap;
   dd qs = {0.0, 0.0}, es = {0.0, 0.0};
   int nonfin = 0;
-  for (int64_t r = (int64_t)blockIdx.x * kRuleBlock + threadIdx.x; r < n;
+  for (int64_t r = start + (int64_t)blockIdx.x * kRuleBlock + threadIdx.x; r < end;
        r += (int64_t)gridDim.x * kRuleBlock) {
     double c[D], h[D];
 #pragma unroll
@@ -366,14 +389,16 @@ __global__ __launch_bounds__(kRuleBlock) void rule_tpr_kernel(RuleArgs A) {
       c[j] = Cb[j * cap + r];
       h[j] = Hb[j * cap + r];
     }
-    const double vol = ldexp(A.vol_omega, -(int)Lb[r]);
-    const RegionResult o = rule_region_tpr<D, FAM>(A.P, A.K, c, h, vol);
+    double volo;
+    const DevParams& P = region_params<BATCH>(A, buf, r, volo);
+    const double vol = ldexp(volo, -(int)Lb[r]);
+    const RegionResult o = rule_region_tpr<D, FAM>(P, A.K, c, h, vol);
     store_result(A, r, o);
     dd_add(qs, o.q);
     dd_add(es, o.err);
     nonfin |= o.nonfinite;
   }
-  block_partials(A, qs, es, nonfin);
+  if constexpr (!BATCH) block_partials(A, qs, es, nonfin);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,7 +430,7 @@ __device__ __forceinline__ double chain_tail(double s, const double* tc, int k0)
   return s;
 }
 
-template <int D, int FAM, int LOG2L>
+template <int D, int FAM, int LOG2L, bool BATCH>
 __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
   using F = Fam<FAM>;
   constexpr int L = 1 << LOG2L;
@@ -413,23 +438,25 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
   constexpr int NPAIR = D * (D - 1) / 2;
   constexpr int NITEM = D + NPAIR;
   __shared__ WprSlot<D> slots[RPB];
-  int64_t n;
+  int64_t start, n;
   int buf;
-  if (!active_range(A, n, buf)) return;
+  if (!active_range<BATCH>(A, start, n, buf)) return;
   const double* __restrict__ Cb = A.C[buf];
   const double* __restrict__ Hb = A.H[buf];
   const uint16_t* __restrict__ Lb = A.L[buf];
   const int64_t cap = A.cap;
   const RuleConsts& K = A.K;
-  const DevParams& P = A.P;
   const int g = threadIdx.x >> LOG2L;  // region slot in the block
   const int s = threadIdx.x & (L - 1);
   WprSlot<D>& sl = slots[g];
   dd qs = {0.0, 0.0}, es = {0.0, 0.0};
   int nonfin = 0;
-  for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
+  for (int64_t base = start + (int64_t)blockIdx.x * RPB; base < n;
+       base += (int64_t)gridDim.x * RPB) {
     const int64_t r = base + g;
     const bool valid = r < n;
+    double volo;
+    const DevParams& P = region_params<BATCH>(A, buf, valid ? r : start, volo);
     double c[D], h[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -523,7 +550,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
     o.err = 0.0;
     o.nonfinite = 0;
     if (s == 0 && valid) {
-      const double vol = ldexp(A.vol_omega, -(int)Lb[r]);
+      const double vol = ldexp(volo, -(int)Lb[r]);
       rule_combine(K, f0, ks_val(S2), ks_val(S3), ks_val(S4), ks_val(S5), vol, o);
       double dmax = -1.0, scale = 0.0;
       for (int i = 0; i < D; ++i) {
@@ -555,7 +582,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
     }
     __syncthreads();
   }
-  block_partials(A, qs, es, nonfin);
+  if constexpr (!BATCH) block_partials(A, qs, es, nonfin);
 }
 
 // ---------------------------------------------------------------------------
@@ -566,44 +593,43 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
 #error "compile with -DGM_RULE_FAMILY=<1..7>"
 #endif
 
-using RuleFn = void (*)(RuleArgs);
-
-template <int D>
-static RuleFn pick(int log2l) {
+template <int D, bool B>
+static RuleKernelFn pick(int log2l) {
   constexpr int F = GM_RULE_FAMILY;
   if (log2l < 0) {
-    if constexpr (D <= kTprMaxDim) return rule_tpr_kernel<D, F>;
+    if constexpr (D <= kTprMaxDim) return rule_tpr_kernel<D, F, B>;
     return nullptr;
   }
   if constexpr (D >= 6) {
-    if (log2l == 2) return rule_wpr_kernel<D, F, 2>;
+    if (log2l == 2) return rule_wpr_kernel<D, F, 2, B>;
     if constexpr (D >= 8) {
-      if (log2l == 4) return rule_wpr_kernel<D, F, 4>;
+      if (log2l == 4) return rule_wpr_kernel<D, F, 4, B>;
     }
     if constexpr (D >= 10) {
-      if (log2l == 6) return rule_wpr_kernel<D, F, 6>;
+      if (log2l == 6) return rule_wpr_kernel<D, F, 6, B>;
     }
   }
   return nullptr;
 }
 
-static RuleFn rule_fn(int d, int log2l) {
+template <bool B>
+static RuleKernelFn rule_fn(int d, int log2l) {
   switch (d) {
-    case 2: return pick<2>(log2l);
-    case 3: return pick<3>(log2l);
-    case 4: return pick<4>(log2l);
-    case 5: return pick<5>(log2l);
-    case 6: return pick<6>(log2l);
-    case 7: return pick<7>(log2l);
-    case 8: return pick<8>(log2l);
-    case 9: return pick<9>(log2l);
-    case 10: return pick<10>(log2l);
-    case 11: return pick<11>(log2l);
-    case 12: return pick<12>(log2l);
-    case 13: return pick<13>(log2l);
-    case 14: return pick<14>(log2l);
-    case 15: return pick<15>(log2l);
-    case 16: return pick<16>(log2l);
+    case 2: return pick<2, B>(log2l);
+    case 3: return pick<3, B>(log2l);
+    case 4: return pick<4, B>(log2l);
+    case 5: return pick<5, B>(log2l);
+    case 6: return pick<6, B>(log2l);
+    case 7: return pick<7, B>(log2l);
+    case 8: return pick<8, B>(log2l);
+    case 9: return pick<9, B>(log2l);
+    case 10: return pick<10, B>(log2l);
+    case 11: return B ? nullptr : pick<11, false>(log2l);
+    case 12: return B ? nullptr : pick<12, false>(log2l);
+    case 13: return B ? nullptr : pick<13, false>(log2l);
+    case 14: return B ? nullptr : pick<14, false>(log2l);
+    case 15: return B ? nullptr : pick<15, false>(log2l);
+    case 16: return B ? nullptr : pick<16, false>(log2l);
     default: return nullptr;
   }
 }
@@ -611,12 +637,8 @@ static RuleFn rule_fn(int d, int log2l) {
 #define GM_CAT2(a, b) a##b
 #define GM_CAT(a, b) GM_CAT2(a, b)
 
-hipError_t GM_CAT(launch_rule_f, GM_RULE_FAMILY)(int d, int log2l, const RuleArgs& a, int grid,
-                                                 hipStream_t s) {
-  RuleFn fn = rule_fn(d, log2l);
-  if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kRuleBlock), 0, s, a);
-  return hipGetLastError();
+RuleKernelFn GM_CAT(rule_kernel_f, GM_RULE_FAMILY)(int d, int log2l, bool batch) {
+  return batch ? rule_fn<true>(d, log2l) : rule_fn<false>(d, log2l);
 }
 
 }  // namespace gm

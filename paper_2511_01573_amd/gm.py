@@ -26,7 +26,7 @@ EINVAL, ENOMEM, EHIP = -1, -2, -3
 EXPORTED = [
     "gm_integrate", "gm_integrate_batch", "gm_integrate_grad", "gm_eval_regions",
     "gm_set_workspace", "gm_workspace_bytes", "gm_set_option", "gm_status_string",
-    "gm_last_stats", "gm_num_nodes", "gm_last_active",
+    "gm_last_stats", "gm_num_nodes", "gm_last_active", "gm_set_tile",
 ]
 
 
@@ -95,6 +95,8 @@ def lib():
         L.gm_last_stats.argtypes = [C.POINTER(Stats)]
         L.gm_num_nodes.restype = C.c_int64
         L.gm_num_nodes.argtypes = [C.c_int]
+        L.gm_set_tile.restype = C.c_int
+        L.gm_set_tile.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.gm_last_active.restype = C.c_int64
         L.gm_last_active.argtypes = [C.c_int64, dp, dp, i32p, dp, dp, i32p]
         _lib = L
@@ -141,6 +143,11 @@ def last_stats() -> dict:
     s = Stats()
     _check(lib().gm_last_stats(C.byref(s)))
     return s.as_dict()
+
+
+def set_tile(d: int, family, lanes_per_region: int, grid_blocks: int = 0) -> None:
+    """Tile shape of the batched rule kernel for (d, family) (autotuner output)."""
+    _check(lib().gm_set_tile(int(d), family_id(family), int(lanes_per_region), int(grid_blocks)))
 
 
 def num_nodes(d: int) -> int:
