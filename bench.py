@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--taus", default="1e-3,1e-5,1e-7")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-oracle sample")
+    ap.add_argument("--batch-sample", type=int, default=512,
+                    help="integrals of the batch run one call each for the comparison")
+    ap.add_argument("--grad-tau", type=float, default=1e-6)
+    ap.add_argument("--grad-log2cap", type=int, default=27)
     return ap.parse_args()
 
 
@@ -92,6 +96,81 @@ def cpu_baseline(budget_s: float):
     return {"value": evals / secs, "unit": "integrand evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{len(names)} full oracle runs of the d=8 workload at rel_tol 1e-3/1e-5 "
                       f"({', '.join(names)}); {evals} evals in {secs:.1f} s, serial C, 1 thread"}
+
+
+def bench_batch(gm, W, closed_forms, sample: int):
+    """C4: 4096 integrals (d 3..10, Gaussian/oscillatory/product peak, rel_tol
+    10^U(-7,-3)) in one gm_integrate_batch call, against one gm_integrate call
+    per integral on a sample of the same items (same tolerances, so the same
+    results)."""
+    import torch
+    from paper_2511_01573_amd import autotune
+    b = W.config4()
+    args = (b["families"], b["params"], b["ds"], b["los"], b["his"], b["rel_tols"], b["abs_tols"])
+    table = autotune.load()
+    gm.set_option("graph_iters", 8)
+    cap = 1 << 26
+    try:
+        gm.integrate_batch(*args, cap)  # warm-up (module load, workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, est, err, st = gm.integrate_batch(*args, cap)
+        tb = time.perf_counter() - t0
+    finally:
+        gm.set_option("graph_iters", 0)
+    n = len(b["families"])
+    idx = list(range(0, n, max(1, n // sample)))[:sample]
+    t0 = time.perf_counter()
+    single = []
+    for i in idx:
+        single.append(gm.integrate(b["families"][i], b["params"][i], b["los"][i], b["his"][i],
+                                   b["rel_tols"][i], b["abs_tols"][i], cap)[0])
+    ts = time.perf_counter() - t0
+    agree = max(abs(single[k] - est[i]) / max(abs(est[i]), 1e-300) for k, i in enumerate(idx))
+    relerr = []
+    for i in range(0, n, 64):
+        d = b["ds"][i]
+        ex = float(closed_forms.exact(b["families"][i], b["params"][i][:d], b["params"][i][d:]))
+        relerr.append(abs(est[i] - ex) / abs(ex))
+    return {"integrals": n, "batch_s": tb, "batch_integrals_per_s": n / tb,
+            "single_sample": len(idx), "single_s": ts, "single_integrals_per_s": len(idx) / ts,
+            "speedup": (n / tb) / (len(idx) / ts), "status_counts": {str(k): int((st == k).sum()) for k in set(st.tolist())},
+            "max_rel_diff_batch_vs_single": agree,
+            "max_rel_err_vs_closed_form_every_64th": max(relerr),
+            "tile_table": "autotuned" if table else "default"}
+
+
+def bench_grad(gm, W, closed_forms, tau: float, cap: int):
+    """C5 gradient (d = 8 Gaussian, 16 parameters): one gm_integrate_grad call
+    against 1 + 32 gm_integrate calls (the estimate plus central differences
+    h = 1e-6 of full adaptive runs), both compared with the erf closed form."""
+    import numpy as np
+    c = W.config5()
+    p = c["params"]
+    d = 8
+    a, u = p[:d], p[d:]
+    want = np.array([float(x) for x in closed_forms.gaussian_grad(a, u)])
+    exact = float(closed_forms.gaussian(a, u))
+    gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)  # warm-up
+    t0 = time.perf_counter()
+    I, E, g, st = gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
+    tg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    I0 = gm.integrate(4, p, c["lo"], c["hi"], tau, 1e-16, cap)[0]
+    fd = np.zeros(2 * d)
+    for k in range(2 * d):
+        pp, pm = p.copy(), p.copy()
+        pp[k] += 1e-6
+        pm[k] -= 1e-6
+        fd[k] = (gm.integrate(4, pp, c["lo"], c["hi"], tau, 1e-16, cap)[0] -
+                 gm.integrate(4, pm, c["lo"], c["hi"], tau, 1e-16, cap)[0]) / 2e-6
+    tf = time.perf_counter() - t0
+    scale = np.abs(want).max()
+    return {"d": d, "rel_tol": tau, "max_regions": cap, "status": st,
+            "grad_s": tg, "fd_s": tf, "speedup": tf / tg,
+            "integral_rel_err": abs(I - exact) / exact,
+            "grad_max_err_rel_to_max": float(np.abs(g - want).max() / scale),
+            "fd_max_err_rel_to_max": float(np.abs(fd - want).max() / scale)}
 
 
 def main():
@@ -150,6 +229,11 @@ def main():
         "cases": [{k: c[k] for k in ("name", "status", "seconds", "evals", "regions", "iterations",
                                      "I", "E")} for c in last],
     }
+    if not args.no_modes:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import closed_forms
+        out["batch"] = bench_batch(gm, W, closed_forms, args.batch_sample)
+        out["grad"] = bench_grad(gm, W, closed_forms, args.grad_tau, 1 << args.grad_log2cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

@@ -1,7 +1,7 @@
 """Build libgm.so (HIP, gfx950) in-tree.
 
-The rule kernel is compiled once per integrand family (-DGM_RULE_FAMILY=k) so
-the objects build in parallel; everything links into
+The rule and adjoint kernels are compiled once per integrand family
+(-DGM_RULE_FAMILY=k / -DGM_FAMILY=k) so the objects build in parallel; everything links into
 paper_2511_01573_amd/libgm.so.  Flags: FP64 code with no implicit FMA
 contraction (-ffp-contract=off; fused multiply-adds are written explicitly),
 packed-FP32 instructions disabled.
@@ -27,15 +27,18 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-ffp-contract=off", "-f
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 FAMILIES = range(1, 8)
+# translation units compiled once per integrand family (template-heavy kernels)
+PER_FAMILY = ("gm_rule", "gm_adjoint")
 
 
 def _units():
     units = []
     for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
         name = os.path.splitext(os.path.basename(src))[0]
-        if name == "gm_rule":
+        if name in PER_FAMILY:
             for f in FAMILIES:
-                units.append((src, os.path.join(BUILD, f"{name}_f{f}.o"), [f"-DGM_RULE_FAMILY={f}"]))
+                units.append((src, os.path.join(BUILD, f"{name}_f{f}.o"),
+                              [f"-DGM_RULE_FAMILY={f}", f"-DGM_FAMILY={f}"]))
         else:
             units.append((src, os.path.join(BUILD, f"{name}.o"), []))
     return units

@@ -1,0 +1,33 @@
+// gm_adjoint.hpp -- declarations of the gradient-mode adjoint kernels.
+#pragma once
+
+#include "gm_common.hpp"
+
+namespace gm {
+
+constexpr int kAdjBlock = 128;
+constexpr int kMaxAdjGrid = 4096;
+
+struct AdjArgs {
+  DevParams P;
+  RuleConsts K;
+  const double* C;
+  const double* H;
+  const uint16_t* L;
+  int64_t cap;
+  int64_t n;
+  double vol_omega;
+  double* partials;  // [grid][2*kMaxDim][2] double-double
+};
+
+using AdjFn = void (*)(AdjArgs);
+// One per family translation unit; nullptr for the polynomial (no parameters).
+AdjFn adjoint_kernel_f1(int d);
+AdjFn adjoint_kernel_f2(int d);
+AdjFn adjoint_kernel_f3(int d);
+AdjFn adjoint_kernel_f4(int d);
+AdjFn adjoint_kernel_f5(int d);
+AdjFn adjoint_kernel_f6(int d);
+AdjFn adjoint_kernel_f7(int d);
+
+}  // namespace gm

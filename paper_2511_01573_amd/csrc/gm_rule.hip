@@ -26,6 +26,7 @@
 //        across the L lanes with shuffles.
 // Class sums are compensated (TwoSum per 16 corners or per node).
 #include "gm_common.hpp"
+#include "gm_math.hpp"
 
 namespace gm {
 
@@ -62,7 +63,7 @@ struct Fam {
   template <int D>
   __device__ static __forceinline__ double outer(const DevParams& P, double s) {
     if constexpr (FAM == kOsc) {
-      return cos(P.c0 + s);
+      return fm::cos(P.c0 + s);
     } else if constexpr (FAM == kProductPeak) {
       return 1.0 / s;
     } else if constexpr (FAM == kCornerPeak) {
@@ -82,9 +83,9 @@ struct Fam {
       }
       return 1.0 / y;
     } else if constexpr (FAM == kGaussian || FAM == kC0) {
-      return exp(-s);
+      return fm::exp(-s);
     } else if constexpr (FAM == kDiscontinuous) {
-      return exp(s);
+      return fm::exp(s);
     } else {
       const double s2 = s * s;
       const double s4 = s2 * s2;

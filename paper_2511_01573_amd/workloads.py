@@ -108,7 +108,7 @@ def config5():
     a = rng.uniform(1.0, 5.0, d)
     u = rng.uniform(0.0, 1.0, d)
     return dict(family=GAUSSIAN, params=np.concatenate([a, u]), lo=np.zeros(d), hi=np.ones(d),
-                rel_tol=1e-8, abs_tol=1e-16, max_regions=1 << 24)
+                rel_tol=1e-8, abs_tol=1e-16, max_regions=1 << 27)
 
 
 def random_regions(d: int, n: int, seed: int, lo=None, hi=None):

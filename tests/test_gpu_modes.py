@@ -1,0 +1,130 @@
+"""Gradient and batched modes on the GPU against the CPU oracle, central
+finite differences of the frozen-tree quadrature, and the Gaussian closed
+form (BASELINE workloads: d = 8 Gaussian gradient, mixed-dimension batch)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+from oracle import oracle as O
+from paper_2511_01573_amd import gm, workloads as W
+from parity import I_TOL
+
+pytestmark = pytest.mark.gpu
+
+
+def grad_scale(res_oracle):
+    return max(np.abs(res_oracle["grad"]).max(), 1e-300)
+
+
+@pytest.mark.parametrize("fam", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("d", [3, 5])
+def test_grad_matches_oracle(fam, d):
+    p = W.family_params(fam, d, seed=500 + 10 * fam + d)
+    tau = 1e-5
+    print(f"case grad fam={fam} d={d}", flush=True)
+    I, E, g, st = gm.integrate_grad(fam, p, *W.unit_box(d), tau)
+    ref = O.integrate_grad(fam, p, *W.unit_box(d), tau)
+    assert st == ref["status"]
+    assert abs(I - ref["I"]) <= I_TOL * abs(ref["I"]) + 1e-300
+    # per-node derivative sums in a different grouping: 1e-12 of the largest component
+    scale = grad_scale(ref)
+    assert np.abs(g - ref["grad"]).max() <= 1e-12 * scale, (g, ref["grad"])
+
+
+def test_grad_gaussian_closed_form_and_fixed_tree_fd():
+    d = 4
+    rng = np.random.default_rng(44)
+    a = rng.uniform(1, 5, d)
+    u = rng.uniform(0, 1, d)
+    p = np.concatenate([a, u])
+    I, E, g, st = gm.integrate_grad(4, p, *W.unit_box(d), 1e-9)
+    assert st == gm.OK
+    want = np.array([float(x) for x in cf.gaussian_grad(a, u)])
+    assert np.abs(g - want).max() <= 1e-7 * np.abs(want).max()
+    # central differences (h = 1e-6) of the oracle's frozen tree of the same run
+    ref = O.integrate_grad(4, p, *W.unit_box(d), 1e-9)
+    c, h, lvl = ref["leaves"]
+    fd = np.zeros(2 * d)
+    for k in range(2 * d):
+        pp, pm = p.copy(), p.copy()
+        pp[k] += 1e-6
+        pm[k] -= 1e-6
+        qp, _ = O.quad_leaves(4, pp, c, h, lvl, ref["vol_omega"])
+        qm, _ = O.quad_leaves(4, pm, c, h, lvl, ref["vol_omega"])
+        fd[k] = (qp - qm) / 2e-6
+    assert np.abs(g - fd).max() <= 1e-7 * np.abs(want).max()
+
+
+def test_grad_config5_d8_gaussian_closed_form():
+    c = W.config5()
+    I, E, g, st = gm.integrate_grad(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"],
+                                    c["abs_tol"], c["max_regions"])
+    assert st == gm.OK
+    d = 8
+    a, u = c["params"][:d], c["params"][d:]
+    exact = float(cf.gaussian(a, u))
+    assert abs(I - exact) <= 1e-7 * exact
+    want = np.array([float(x) for x in cf.gaussian_grad(a, u)])
+    assert np.abs(g - want).max() <= 1e-6 * np.abs(want).max()
+
+
+def small_batch(n, seed, dmin=3, dmax=6, fams=(1, 2, 4, 3, 5)):
+    rng = np.random.default_rng(seed)
+    fl, pl, dl, lo, hi, rt, at = [], [], [], [], [], [], []
+    for i in range(n):
+        d = int(rng.integers(dmin, dmax + 1))
+        fam = int(fams[int(rng.integers(0, len(fams)))])
+        pl.append(W.family_params(fam, d, seed=seed * 100000 + i))
+        fl.append(fam)
+        dl.append(d)
+        lo.append(np.zeros(d))
+        hi.append(np.ones(d))
+        rt.append(10 ** rng.uniform(-6, -3))
+        at.append(1e-16)
+    return fl, pl, dl, lo, hi, rt, at
+
+
+@pytest.mark.parametrize("graph_iters", [0, 4])
+def test_batch_matches_oracle_lockstep(graph_iters):
+    b = small_batch(96, seed=7)
+    gm.set_option("init_log2_regions", 6)
+    gm.set_option("graph_iters", graph_iters)
+    try:
+        print(f"case batch graph_iters={graph_iters}", flush=True)
+        rc, est, err, st = gm.integrate_batch(*b, 1 << 22)
+    finally:
+        gm.set_option("init_log2_regions", 12)
+        gm.set_option("graph_iters", 0)
+    orc, oest, oerr, ost, oits = O.integrate_batch(*b, 1 << 22, init_log2=6)
+    assert rc == orc
+    assert np.array_equal(st, ost)
+    assert np.all(np.abs(est - oest) <= I_TOL * np.abs(oest) + 1e-300), np.max(np.abs(est - oest) / np.abs(oest))
+    # each item equals its own single-integral run
+    for i in range(0, 96, 17):
+        gm.set_option("init_log2_regions", 6)
+        try:
+            I, E, s1 = gm.integrate(b[0][i], b[1][i], b[3][i], b[4][i], b[5][i], 1e-16, 1 << 22)
+        finally:
+            gm.set_option("init_log2_regions", 12)
+        assert s1 == st[i] and I == est[i] and E == err[i]
+
+
+def test_batch_shared_capacity_and_invalid_items():
+    fl = [4, 4, 4]
+    pl = [np.array([2.0, 2.0, 0.5, 0.5]), np.array([30.0, 30.0, 0.3, 0.3]), np.ones(24)]
+    dl = [2, 2, 12]
+    lo = [np.zeros(2), np.zeros(2), np.zeros(12)]
+    hi = [np.ones(2), np.ones(2), np.ones(12)]
+    gm.set_option("init_log2_regions", 4)
+    try:
+        rc, est, err, st = gm.integrate_batch(fl, pl, dl, lo, hi, [1e-3, 1e-10, 1e-3],
+                                              [1e-16] * 3, 3000)
+    finally:
+        gm.set_option("init_log2_regions", 12)
+    assert st[2] == gm.EINVAL and np.isnan(est[2])  # d > 10 is not a batch item
+    orc, oest, oerr, ost, oits = O.integrate_batch(fl[:2], pl[:2], dl[:2], lo[:2], hi[:2],
+                                                   [1e-3, 1e-10], [1e-16] * 2, 3000, init_log2=4)
+    assert list(st[:2]) == list(ost) == [gm.OK, gm.MAX_REGIONS]
+    assert np.all(np.abs(est[:2] - oest) <= I_TOL * np.abs(oest))
