@@ -282,7 +282,10 @@ struct ScatterArgs {
 
 // Split + stable compaction (Sec. 3: filtering and splitting fused).  Ranks
 // inside a tile come from wavefront ballots and an LDS prefix over the four
-// wavefronts; the tile's base offset comes from the scan kernel.
+// wavefronts; the tile's base offset comes from the scan kernel.  The
+// dimension is a template parameter so every coordinate load of a region is
+// issued before its stores.
+template <int D>
 __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
   const Status* st = A.st;
   if (st->done) return;
@@ -325,30 +328,30 @@ __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
       const int64_t before = off + __popcll(masks[k] & ((1ull << lane) - 1ull));
       if (keepv[k]) {
         const int64_t p0 = before, p1 = nk + before;
-        const int ax = A.AXIS[r] & 0x7f;
-        for (int j = 0; j < A.d; ++j) {
-          const double cj = Ci[j * cap + r];
-          const double hj = Hi[j * cap + r];
-          if (j == ax) {
-            const double hp = hj * 0.5;
-            Co[j * cap + p0] = cj - hp;
-            Co[j * cap + p1] = cj + hp;
-            Ho[j * cap + p0] = hp;
-            Ho[j * cap + p1] = hp;
-          } else {
-            Co[j * cap + p0] = cj;
-            Co[j * cap + p1] = cj;
-            Ho[j * cap + p0] = hj;
-            Ho[j * cap + p1] = hj;
-          }
+        const int ax = A.AXIS[r] & kAxisMask;
+        double c[D], h[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          c[j] = Ci[j * cap + r];
+          h[j] = Hi[j * cap + r];
         }
         const uint16_t l1 = (uint16_t)(Li[r] + 1);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const double hp = h[j] * 0.5;
+          const bool sp = (j == ax);
+          Co[j * cap + p0] = sp ? c[j] - hp : c[j];
+          Co[j * cap + p1] = sp ? c[j] + hp : c[j];
+          Ho[j * cap + p0] = sp ? hp : h[j];
+          Ho[j * cap + p1] = sp ? hp : h[j];
+        }
         Lo[p0] = l1;
         Lo[p1] = l1;
       } else if (A.LC != nullptr && r < n) {
         const int64_t slot = leaf_base + (r - before);
         if (slot < A.leaf_cap) {
-          for (int j = 0; j < A.d; ++j) {
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
             A.LC[j * A.leaf_cap + slot] = Ci[j * cap + r];
             A.LH[j * A.leaf_cap + slot] = Hi[j * cap + r];
           }
@@ -358,6 +361,29 @@ __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
       base += rowtot;
     }
     __syncthreads();
+  }
+}
+
+using ScatterFn = void (*)(ScatterArgs);
+
+static ScatterFn scatter_fn(int d) {
+  switch (d) {
+    case 2: return scatter_kernel<2>;
+    case 3: return scatter_kernel<3>;
+    case 4: return scatter_kernel<4>;
+    case 5: return scatter_kernel<5>;
+    case 6: return scatter_kernel<6>;
+    case 7: return scatter_kernel<7>;
+    case 8: return scatter_kernel<8>;
+    case 9: return scatter_kernel<9>;
+    case 10: return scatter_kernel<10>;
+    case 11: return scatter_kernel<11>;
+    case 12: return scatter_kernel<12>;
+    case 13: return scatter_kernel<13>;
+    case 14: return scatter_kernel<14>;
+    case 15: return scatter_kernel<15>;
+    case 16: return scatter_kernel<16>;
+    default: return nullptr;
   }
 }
 
@@ -728,14 +754,26 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
     GM_HIP(hipGetLastError());
   }
 
-  hipEvent_t ev[6] = {};
+  // Iterations launched back to back before the host reads the status
+  // block: kernels take the active count from the device and return at once
+  // after a final status, so launches past the end cost only their launch.
+  // Grids are sized for the largest count the iteration can have (n doubles
+  // at most per iteration).  Gradient mode checks every iteration (the leaf
+  // store grows on the host's side).
+  constexpr int kMaxAhead = 8;
+  hipEvent_t ev[kMaxAhead][5] = {};
   const bool timing = g_opt.timing != 0;
   if (timing)
-    for (auto& e : ev) GM_HIP(hipEventCreate(&e));
+    for (auto& row : ev)
+      for (auto& e : row) GM_HIP(hipEventCreate(&e));
 
   int64_t n = n0;
   int64_t leaves_have = 0;
+  int64_t iter_done = 0;
   for (;;) {
+    int K = 1;
+    if (!keep_leaves)
+      K = g_opt.graph_iters > 0 ? std::min(g_opt.graph_iters, kMaxAhead) : (n < (1 << 18) ? 4 : 1);
     if (keep_leaves) {
       // Room for every region of this iteration to retire.
       rc = leaf_reserve(d, leaves_have + n, leaves_have, s);
@@ -745,47 +783,57 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       sa.LL = g_leaves.L;
       sa.leaf_cap = g_leaves.cap;
     }
-    const int map = choose_mapping(d, n);
-    const int rg = rule_grid(map, n);
-    const int tg = tile_grid_for(n);
-    g_stats.lanes_per_region = map < 0 ? 1 : (1 << map);
-    if (timing) GM_HIP(hipEventRecord(ev[0], s));
-    GM_HIP(launch_rule(d, fam, map, ra, rg, s));
-    if (timing) GM_HIP(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, st, ra.partials, rg);
-    GM_HIP(hipGetLastError());
-    if (timing) GM_HIP(hipEventRecord(ev[2], s));
-    hipLaunchKernelGGL(classify_kernel, dim3(tg), dim3(kTileThreads), 0, s, ca);
-    GM_HIP(hipGetLastError());
-    if (timing) GM_HIP(hipEventRecord(ev[3], s));
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, st, ca.TK, sa.TOFF, ca.TQ, ca.TE);
-    GM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(scatter_kernel, dim3(tg), dim3(kTileThreads), 0, s, sa);
-    GM_HIP(hipGetLastError());
-    if (timing) GM_HIP(hipEventRecord(ev[4], s));
+    int64_t nb = n;
+    for (int k = 0; k < K; ++k) {
+      const int map = choose_mapping(d, nb);
+      const int rg = rule_grid(map, nb);
+      const int tg = tile_grid_for(nb);
+      g_stats.lanes_per_region = map < 0 ? 1 : (1 << map);
+      if (timing) GM_HIP(hipEventRecord(ev[k][0], s));
+      GM_HIP(launch_rule(d, fam, map, ra, rg, s));
+      if (timing) GM_HIP(hipEventRecord(ev[k][1], s));
+      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, st, ra.partials, rg);
+      GM_HIP(hipGetLastError());
+      if (timing) GM_HIP(hipEventRecord(ev[k][2], s));
+      hipLaunchKernelGGL(classify_kernel, dim3(tg), dim3(kTileThreads), 0, s, ca);
+      GM_HIP(hipGetLastError());
+      if (timing) GM_HIP(hipEventRecord(ev[k][3], s));
+      hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, st, ca.TK, sa.TOFF, ca.TQ, ca.TE);
+      GM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(scatter_fn(d), dim3(tg), dim3(kTileThreads), 0, s, sa);
+      GM_HIP(hipGetLastError());
+      if (timing) GM_HIP(hipEventRecord(ev[k][4], s));
+      nb = std::min<int64_t>(cap, 2 * nb);
+    }
     GM_HIP(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
+    const int ran = (int)std::min<int64_t>(K, hst.iter - iter_done);
+    iter_done = hst.iter;
     if (timing) {
-      float a = 0, b = 0, c = 0, e = 0;
-      GM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
-      GM_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
-      GM_HIP(hipEventElapsedTime(&c, ev[2], ev[3]));
-      GM_HIP(hipEventElapsedTime(&e, ev[3], ev[4]));
-      g_stats.rule_ms += a;
-      g_stats.reduce_ms += b;
-      g_stats.classify_ms += c;
-      g_stats.split_ms += e;
-      g_stats.rule_launches += 1;
+      for (int k = 0; k < ran; ++k) {
+        float a = 0, b = 0, c = 0, e = 0;
+        GM_HIP(hipEventElapsedTime(&a, ev[k][0], ev[k][1]));
+        GM_HIP(hipEventElapsedTime(&b, ev[k][1], ev[k][2]));
+        GM_HIP(hipEventElapsedTime(&c, ev[k][2], ev[k][3]));
+        GM_HIP(hipEventElapsedTime(&e, ev[k][3], ev[k][4]));
+        g_stats.rule_ms += a;
+        g_stats.reduce_ms += b;
+        g_stats.classify_ms += c;
+        g_stats.split_ms += e;
+        g_stats.rule_launches += 1;
+      }
     }
     if (g_opt.log)
       std::fprintf(stderr, "gm: iter %lld n %lld I %.17g E %.6g T %.6g done %lld\n",
-                   (long long)hst.iter, (long long)n, hst.I, hst.E, hst.T, (long long)hst.done);
+                   (long long)hst.iter, (long long)hst.n_active, hst.I, hst.E, hst.T,
+                   (long long)hst.done);
     leaves_have = hst.leaf_count;
     if (hst.done) break;
     n = hst.n_active;
   }
   if (timing)
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& row : ev)
+      for (auto& e : row) (void)hipEventDestroy(e);
 
   out->I = hst.I;
   out->E = hst.E;

@@ -11,9 +11,10 @@
 //   form); the result is scaled by 2^k with ldexp, which also produces the
 //   correct underflow to 0 and overflow to +inf.  Arguments below -1100 are
 //   clamped (e^-1100 underflows to 0), which also maps -inf to 0.
-// cos(x): reduction by pi/2 (three-part Cody-Waite with FMAs, valid here for
-//   |x| < 2^20), cos(r) = C(r^2) (degree 7 in r^2) and sin(r) = r S(r^2)
-//   (degree 6), quadrant select; |x| >= 2^20 falls back to the device cos.
+// cos(x): reduction by pi/2 (three-part Cody-Waite with FMAs: pi/2 carried in
+//   three doubles, each product formed exactly inside an FMA; accurate while
+//   |x| < 2^48, the range the kernels admit), cos(r) = C(r^2) (degree 7 in r^2)
+//   and sin(r) = r S(r^2) (degree 6), quadrant select.  No branch.
 // Coefficients: csrc/gen_math_coeffs.py (mpmath, 50 digits).  Both functions
 // compile unchanged for the host, where tests/test_device_math.py measures
 // their error against 50-digit references.
@@ -76,7 +77,6 @@ GM_HD double exp(double x) {
 }
 
 GM_HD double cos(double x) {
-  if (!(fabs(x) < 1048576.0)) return ::cos(x);
   const double t = fma(x, k2OverPi, kShift);
   const double kd = t - kShift;
   const int32_t q = low_word(t);

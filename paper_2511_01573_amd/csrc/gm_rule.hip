@@ -31,6 +31,17 @@
 namespace gm {
 
 constexpr int kRuleBlock = kRuleBlockSize;
+// Unrolling of the class 2/3 and class 4 loops of the one-lane-per-region
+// kernel (full unrolling keeps every index compile-time; a count of 1 keeps
+// the loops and indexes the term arrays with wavefront-uniform counters,
+// which lowers register use).
+#ifndef GM_UNROLL_A23
+#define GM_UNROLL_A23 64
+#endif
+#ifndef GM_UNROLL_A4
+#define GM_UNROLL_A4 64
+#endif
+
 
 // ---------------------------------------------------------------------------
 // Family traits: term, combination and outer function (Sec. 4 integrands).
@@ -59,6 +70,31 @@ struct Fam {
   __device__ static __forceinline__ double comb(double s, double t) {
     if constexpr (kProduct) return s * t;
     else return s + t;
+  }
+  // The oscillatory family's cos is reduced by pi/2 in double-double steps that
+  // stay accurate while |argument| < 2^48; a region whose nodes could exceed that
+  // bound is reported as non-finite instead of evaluated inaccurately.
+  template <int D>
+  __device__ static __forceinline__ bool in_range(const DevParams& P, const double (&c)[D],
+                                                  const double (&h)[D]) {
+    if constexpr (FAM == kOsc) {
+      double b = fabs(P.c0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) b += fabs(P.a[j]) * (fabs(c[j]) + h[j]);
+      return b < 0x1p48;
+    } else {
+      return true;
+    }
+  }
+  __device__ static __forceinline__ bool in_range_rt(const DevParams& P, int d, const double* c,
+                                                     const double* h) {
+    if constexpr (FAM == kOsc) {
+      double b = fabs(P.c0);
+      for (int j = 0; j < d; ++j) b += fabs(P.a[j]) * (fabs(c[j]) + h[j]);
+      return b < 0x1p48;
+    } else {
+      return true;
+    }
   }
   template <int D>
   __device__ static __forceinline__ double outer(const DevParams& P, double s) {
@@ -279,12 +315,12 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
                                                         const double (&c)[D], const double (&h)[D],
                                                         double vol) {
   using F = Fam<FAM>;
-  double tc[D], t2p[D], t2m[D], t3p[D], t3m[D];
+  // Terms at the centre and at +-l3 (= +-l4) per coordinate; the +-l2 terms
+  // are formed where they are used to keep the live register set small.
+  double tc[D], t3p[D], t3m[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) {
     tc[j] = F::term(P, j, c[j]);
-    t2p[j] = F::term(P, j, fma(K.lam2, h[j], c[j]));
-    t2m[j] = F::term(P, j, fma(-K.lam2, h[j], c[j]));
     t3p[j] = F::term(P, j, fma(K.lam3, h[j], c[j]));
     t3m[j] = F::term(P, j, fma(-K.lam3, h[j], c[j]));
   }
@@ -296,15 +332,17 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
   for (int k = 2; k <= D; ++k) pc[k] = F::comb(pc[k - 1], tc[k - 1]);
   const double f0 = F::template outer<D>(P, pc[D]);
   KSum S2 = {0.0, 0.0}, S3 = {0.0, 0.0}, S4 = {0.0, 0.0}, S5 = {0.0, 0.0};
-  double Dv[D], sc[D];
-#pragma unroll
+  double Dv[D];
+  double scale = 0.0;
+#pragma unroll GM_UNROLL_A23
   for (int i = 0; i < D; ++i) {
-    double v[4] = {t2p[i], t2m[i], t3p[i], t3m[i]};
+    const double v[4] = {F::term(P, i, fma(K.lam2, h[i], c[i])),
+                         F::term(P, i, fma(-K.lam2, h[i], c[i])), t3p[i], t3m[i]};
     double f[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       double s = (i == 0) ? v[q] : F::comb(pc[i], v[q]);
-#pragma unroll
+#pragma unroll GM_UNROLL_A23
       for (int k = i + 1; k < D; ++k) s = F::comb(s, tc[k]);
       f[q] = F::template outer<D>(P, s);
     }
@@ -312,20 +350,24 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
     ks_add(S2, f[1]);
     ks_add(S3, f[2]);
     ks_add(S3, f[3]);
-    fourth_diff(K, f0, f[0], f[1], f[2], f[3], Dv[i], sc[i]);
+    double sc;
+    fourth_diff(K, f0, f[0], f[1], f[2], f[3], Dv[i], sc);
+    scale = sc > scale ? sc : scale;
   }
-#pragma unroll
+  // Class 4 walks (i, j) with loop counters that are the same in every lane
+  // of the wavefront, so the term arrays are indexed uniformly.
+#pragma unroll GM_UNROLL_A4
   for (int i = 0; i < D - 1; ++i) {
 #pragma unroll
     for (int si = 0; si < 2; ++si) {
       const double ti = si ? t3m[i] : t3p[i];
       double m = (i == 0) ? ti : F::comb(pc[i], ti);
-#pragma unroll
+#pragma unroll GM_UNROLL_A4
       for (int j = i + 1; j < D; ++j) {
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) {
           double s = F::comb(m, sj ? t3m[j] : t3p[j]);
-#pragma unroll
+#pragma unroll GM_UNROLL_A4
           for (int k = j + 1; k < D; ++k) s = F::comb(s, tc[k]);
           ks_add(S4, F::template outer<D>(P, s));
         }
@@ -333,22 +375,21 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
       }
     }
   }
-  double t5p[D], t5m[D];
+  {
+    double t5p[D], t5m[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) {
-    t5p[j] = F::term(P, j, fma(K.lam5, h[j], c[j]));
-    t5m[j] = F::term(P, j, fma(-K.lam5, h[j], c[j]));
+    for (int j = 0; j < D; ++j) {
+      t5p[j] = F::term(P, j, fma(K.lam5, h[j], c[j]));
+      t5m[j] = F::term(P, j, fma(-K.lam5, h[j], c[j]));
+    }
+    corner_sweep<D, FAM, 0>(P, t5p, t5m, 0u, S5);
   }
-  corner_sweep<D, FAM, 0>(P, t5p, t5m, 0u, S5);
 
   RegionResult r;
   rule_combine(K, f0, ks_val(S2), ks_val(S3), ks_val(S4), ks_val(S5), vol, r);
-  double dmax = -1.0, scale = 0.0;
+  double dmax = -1.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    dmax = Dv[i] > dmax ? Dv[i] : dmax;
-    scale = sc[i] > scale ? sc[i] : scale;
-  }
+  for (int i = 0; i < D; ++i) dmax = Dv[i] > dmax ? Dv[i] : dmax;
   const double thr = dmax - K.axis_band * scale;
   int axis = -1;
   double hb = 0.0, cb = 0.0;
@@ -368,6 +409,7 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
   const double hp = hb * 0.5;
   r.axis = axis;
   r.geo = (cb - hp == cb) || (cb + hp == cb) || (hp == 0.0);
+  r.nonfinite |= !F::in_range(P, c, h);
   return r;
 }
 
@@ -576,6 +618,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
       const double hp = hb * 0.5;
       o.axis = axis;
       o.geo = (cb - hp == cb) || (cb + hp == cb) || (hp == 0.0);
+      o.nonfinite |= !F::in_range_rt(P, D, sl.c, sl.h);
       store_result(A, r, o);
       dd_add(qs, o.q);
       dd_add(es, o.err);
