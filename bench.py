@@ -34,13 +34,14 @@ sys.path.insert(0, ROOT)
 # MI355X published FP64 vector peak (256 CUs x 128 FP64 FLOP/clk x 2.4 GHz).
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
-# FP64 FLOPs per integrand evaluation as the rule kernel implements it (FMA =
-# 2, ADD/MUL = 1; rcp/div counted by their FP64 FMA/MUL/ADD steps), for the
-# corner sweep that carries > 60 % of the nodes at d = 8: about two chained
-# combinations of per-coordinate terms, the outer function, one accumulation.
-# Derivation in the design doc (kernel table); checked against the SQ_INSTS_VALU_*_F64
-# counters in profiles/.
-FLOPS_PER_EVAL = {1: 52.0, 2: 14.0, 3: 22.0, 4: 31.0, 5: 31.0, 6: 31.0, 7: 8.0}
+# FP64 FLOPs per integrand evaluation as the rule kernel implements it:
+# counted from the compiled corner-sweep loop of the one-lane-per-region rule
+# kernel at d = 8 (the loop that evaluates 256 of the 401 nodes of a region),
+# FMA = 2, ADD/MUL/RCP = 1, per corner: the amortized chain combinations of
+# per-coordinate terms, the outer function (exp / cos / reciprocal / powers)
+# and the compensated accumulation.  Cross-checked against the
+# SQ_INSTS_VALU_*_F64 counters (profiles/).
+FLOPS_PER_EVAL = {1: 42.75, 2: 12.75, 3: 17.75, 4: 32.5, 5: 32.75, 6: 32.5, 7: 8.5}
 
 
 def parse():
@@ -57,6 +58,7 @@ def parse():
                     help="integrals of the batch run one call each for the comparison")
     ap.add_argument("--grad-tau", type=float, default=1e-6)
     ap.add_argument("--grad-log2cap", type=int, default=27)
+    ap.add_argument("--config3-log2cap", type=int, default=27)
     return ap.parse_args()
 
 
@@ -109,7 +111,7 @@ def bench_batch(gm, W, closed_forms, sample: int):
     args = (b["families"], b["params"], b["ds"], b["los"], b["his"], b["rel_tols"], b["abs_tols"])
     table = autotune.load()
     gm.set_option("graph_iters", 8)
-    cap = 1 << 26
+    cap = 1 << 28  # shared by all 4096 items (~95 GB at d <= 10)
     try:
         gm.integrate_batch(*args, cap)  # warm-up (module load, workspace)
         torch.cuda.synchronize()
@@ -124,7 +126,7 @@ def bench_batch(gm, W, closed_forms, sample: int):
     single = []
     for i in idx:
         single.append(gm.integrate(b["families"][i], b["params"][i], b["los"][i], b["his"][i],
-                                   b["rel_tols"][i], b["abs_tols"][i], cap)[0])
+                                   b["rel_tols"][i], b["abs_tols"][i], 1 << 26)[0])
     ts = time.perf_counter() - t0
     agree = max(abs(single[k] - est[i]) / max(abs(est[i]), 1e-300) for k, i in enumerate(idx))
     relerr = []
@@ -138,6 +140,28 @@ def bench_batch(gm, W, closed_forms, sample: int):
             "max_rel_diff_batch_vs_single": agree,
             "max_rel_err_vs_closed_form_every_64th": max(relerr),
             "tile_table": "autotuned" if table else "default"}
+
+
+def bench_config3(gm, W, closed_forms, log2cap: int):
+    """d = 12 and 16, corner peak and product peak, rel_tol 1e-4, region store
+    of 2^log2cap rows (the high-dimensional, many-lanes-per-region regime)."""
+    out = []
+    for c in W.config3(max_regions=1 << log2cap):
+        d = len(c["lo"])
+        gm.set_option("timing", 1)
+        t0 = time.perf_counter()
+        I, E, st = gm.integrate(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"],
+                                c["abs_tol"], c["max_regions"])
+        dt = time.perf_counter() - t0
+        s = gm.last_stats()
+        gm.set_option("timing", 0)
+        ex = float(closed_forms.exact(c["family"], c["params"][:d], c["params"][d:]))
+        out.append({"name": c["name"], "status": st, "seconds": dt, "evals": s["evals"],
+                    "regions": s["regions_evaluated"], "iterations": s["iterations"],
+                    "max_active": s["max_active"], "evals_per_s": s["evals"] / dt,
+                    "rule_evals_per_s": s["evals"] / max(s["rule_ms"] * 1e-3, 1e-12),
+                    "rel_err_vs_closed_form": abs(I - ex) / abs(ex), "E_over_I": E / abs(I)})
+    return out
 
 
 def bench_grad(gm, W, closed_forms, tau: float, cap: int):
@@ -225,6 +249,7 @@ def main():
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
                      "rule_kernel_s": rule_s, "rule_launches": launches,
+                     "rule_avg_launch_ms": rule_s / launches * 1e3,
                      "rule_evals_per_s": evals / rule_s},
         "cases": [{k: c[k] for k in ("name", "status", "seconds", "evals", "regions", "iterations",
                                      "I", "E")} for c in last],
@@ -234,6 +259,7 @@ def main():
         import closed_forms
         out["batch"] = bench_batch(gm, W, closed_forms, args.batch_sample)
         out["grad"] = bench_grad(gm, W, closed_forms, args.grad_tau, 1 << args.grad_log2cap)
+        out["config3"] = bench_config3(gm, W, closed_forms, args.config3_log2cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

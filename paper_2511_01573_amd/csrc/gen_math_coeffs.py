@@ -3,8 +3,8 @@ pasted into the header).
 
 exp:  e^r on [-ln2/2, ln2/2], degree 11, Chebyshev approximation (mpmath
       chebyfit, 50 digits) -- max error 3.2e-18.
-cos:  cos(r) = C(z), z = r^2, z in [0, (pi/4)^2], degree 7 in z -- 3.0e-20.
-sin:  sin(r) = r * S(z), degree 6 in z -- 3.1e-18.
+cos:  cos(r) = C(z), z = r^2, z in [0, (pi/2)^2], degree 9 in z -- 6.4e-21
+      (reduction by pi, |r| <= pi/2).
 Coefficients are printed as hexadecimal doubles, highest degree first.
 """
 import mpmath as mp
@@ -25,19 +25,17 @@ def show(name, coeffs, err):
 
 ln2 = mp.log(2)
 show("kExpPoly", *fit(mp.exp, -ln2 / 2, ln2 / 2, 11))
-show("kCosPoly", *fit(lambda z: mp.cos(mp.sqrt(z)) if z > 0 else mp.mpf(1), 0, (mp.pi / 4) ** 2, 7))
-show("kSinPoly", *fit(lambda z: mp.sin(mp.sqrt(z)) / mp.sqrt(z) if z > 0 else mp.mpf(1), 0,
-                      (mp.pi / 4) ** 2, 6))
+show("kCosPoly", *fit(lambda z: mp.cos(mp.sqrt(z)) if z > 0 else mp.mpf(1), 0, (mp.pi / 2) ** 2, 9))
 # Cody-Waite constants
 l2hi = float(ln2)
 l2lo = float(ln2 - mp.mpf(l2hi))
 print("constexpr double kLn2Hi =", l2hi.hex(), ";")
 print("constexpr double kLn2Lo =", l2lo.hex(), ";")
 print("constexpr double kInvLn2 =", float(1 / ln2).hex(), ";")
-p1 = float(mp.pi / 2)
-p2 = float(mp.pi / 2 - mp.mpf(p1))
-p3 = float(mp.pi / 2 - mp.mpf(p1) - mp.mpf(p2))
-print("constexpr double kPio2_1 =", p1.hex(), ";")
-print("constexpr double kPio2_2 =", p2.hex(), ";")
-print("constexpr double kPio2_3 =", p3.hex(), ";")
-print("constexpr double k2OverPi =", float(2 / mp.pi).hex(), ";")
+p1 = float(mp.pi)
+p2 = float(mp.pi - mp.mpf(p1))
+p3 = float(mp.pi - mp.mpf(p1) - mp.mpf(p2))
+print("constexpr double kPi_1 =", p1.hex(), ";")
+print("constexpr double kPi_2 =", p2.hex(), ";")
+print("constexpr double kPi_3 =", p3.hex(), ";")
+print("constexpr double kInvPi =", float(1 / mp.pi).hex(), ";")

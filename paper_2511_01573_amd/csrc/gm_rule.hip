@@ -101,9 +101,9 @@ struct Fam {
     if constexpr (FAM == kOsc) {
       return fm::cos(P.c0 + s);
     } else if constexpr (FAM == kProductPeak) {
-      return 1.0 / s;
+      return fm::rcp(s);
     } else if constexpr (FAM == kCornerPeak) {
-      // (1 + s)^-(d+1): binary powering, then one correctly rounded division
+      // (1 + s)^-(d+1): binary powering, then one reciprocal
       const double b = 1.0 + s;
       double y = 1.0, p = b;
       int e = D + 1;
@@ -117,7 +117,7 @@ struct Fam {
         e >>= 1;
         if (e) p = p * p;
       }
-      return 1.0 / y;
+      return fm::rcp(y);
     } else if constexpr (FAM == kGaussian || FAM == kC0) {
       return fm::exp(-s);
     } else if constexpr (FAM == kDiscontinuous) {
