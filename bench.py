@@ -21,8 +21,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -43,6 +45,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # SQ_INSTS_VALU_*_F64 counters (profiles/).
 FLOPS_PER_EVAL = {1: 42.75, 2: 12.75, 3: 17.75, 4: 32.5, 5: 32.75, 6: 32.5, 7: 8.5}
 
+# HBM traffic of the rule kernel, per launch, measured with rocprofv3 --pmc
+# (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+# plain device copy of known size) on this benchmark's own launches.  The
+# summary file records the SHA-256 of the sources the rule kernel is compiled
+# from; the figure is reported only while those sources are unchanged.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rule_kernel_d8_suite_counters.md")
+RULE_SOURCES = [os.path.join(ROOT, "paper_2511_01573_amd", "csrc", f)
+                for f in ("gm_rule.hip", "gm_common.hpp", "gm_math.hpp", "gm_api.hip")]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -54,12 +65,46 @@ def parse():
     ap.add_argument("--taus", default="1e-3,1e-5,1e-7")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-oracle sample")
-    ap.add_argument("--batch-sample", type=int, default=512,
-                    help="integrals of the batch run one call each for the comparison")
     ap.add_argument("--grad-tau", type=float, default=1e-6)
     ap.add_argument("--grad-log2cap", type=int, default=27)
     ap.add_argument("--config3-log2cap", type=int, default=27)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
+
+
+def rule_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for f in RULE_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Rule-kernel HBM bytes per launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m_sha = re.search(r"rule_sources_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"hbm_bytes_per_rule_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_val or m_sha.group(1) != rule_sources_sha256():
+        return None
+    return float(m_val.group(1))
+
+
+def copy_calibration():
+    """A plain 1 GiB device copy, the reference that scales the HBM counters."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
 
 
 def run_cases(gm, cases):
@@ -100,45 +145,51 @@ def cpu_baseline(budget_s: float):
                       f"({', '.join(names)}); {evals} evals in {secs:.1f} s, serial C, 1 thread"}
 
 
-def bench_batch(gm, W, closed_forms, sample: int):
-    """C4: 4096 integrals (d 3..10, Gaussian/oscillatory/product peak, rel_tol
-    10^U(-7,-3)) in one gm_integrate_batch call, against one gm_integrate call
-    per integral on a sample of the same items (same tolerances, so the same
-    results)."""
+def bench_batch(gm, W, closed_forms):
+    """4096 integrals (d 3..10, Gaussian/oscillatory/product peak, rel_tol
+    10^U(-7,-3)) in one gm_integrate_batch call (shared store of 2^28 regions,
+    graph replay of 8 iterations), against one gm_integrate call per integral
+    over the same 4096 items (same tolerances; every item converges both ways,
+    so both give each item's own adaptive result)."""
     import torch
     from paper_2511_01573_amd import autotune
     b = W.config4()
     args = (b["families"], b["params"], b["ds"], b["los"], b["his"], b["rel_tols"], b["abs_tols"])
     table = autotune.load()
     gm.set_option("graph_iters", 8)
-    cap = 1 << 28  # shared by all 4096 items (~95 GB at d <= 10)
+    cap = 1 << 28  # shared by all 4096 items (~88 GiB at d <= 10)
     try:
         gm.integrate_batch(*args, cap)  # warm-up (module load, workspace)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, est, err, st = gm.integrate_batch(*args, cap)
         tb = time.perf_counter() - t0
+        bstats = gm.last_stats()
     finally:
         gm.set_option("graph_iters", 0)
     n = len(b["families"])
-    idx = list(range(0, n, max(1, n // sample)))[:sample]
+    gm.integrate(b["families"][0], b["params"][0], b["los"][0], b["his"][0], b["rel_tols"][0],
+                 b["abs_tols"][0], 1 << 26)  # warm-up of the single path
     t0 = time.perf_counter()
-    single = []
-    for i in idx:
-        single.append(gm.integrate(b["families"][i], b["params"][i], b["los"][i], b["his"][i],
-                                   b["rel_tols"][i], b["abs_tols"][i], 1 << 26)[0])
+    single, sst = np.zeros(n), np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        single[i], _, sst[i] = gm.integrate(b["families"][i], b["params"][i], b["los"][i],
+                                            b["his"][i], b["rel_tols"][i], b["abs_tols"][i], 1 << 26)
     ts = time.perf_counter() - t0
-    agree = max(abs(single[k] - est[i]) / max(abs(est[i]), 1e-300) for k, i in enumerate(idx))
+    agree = float(np.max(np.abs(single - est) / np.maximum(np.abs(est), 1e-300)))
     relerr = []
-    for i in range(0, n, 64):
+    for i in range(0, n, 16):
         d = b["ds"][i]
         ex = float(closed_forms.exact(b["families"][i], b["params"][i][:d], b["params"][i][d:]))
         relerr.append(abs(est[i] - ex) / abs(ex))
     return {"integrals": n, "batch_s": tb, "batch_integrals_per_s": n / tb,
-            "single_sample": len(idx), "single_s": ts, "single_integrals_per_s": len(idx) / ts,
-            "speedup": (n / tb) / (len(idx) / ts), "status_counts": {str(k): int((st == k).sum()) for k in set(st.tolist())},
+            "batch_evals": bstats["evals"], "batch_evals_per_s": bstats["evals"] / tb,
+            "single_s": ts, "single_integrals_per_s": n / ts, "speedup": ts / tb,
+            "status_counts_batch": {str(k): int((st == k).sum()) for k in set(st.tolist())},
+            "status_counts_single": {str(k): int((sst == k).sum()) for k in set(sst.tolist())},
             "max_rel_diff_batch_vs_single": agree,
-            "max_rel_err_vs_closed_form_every_64th": max(relerr),
+            "max_rel_err_vs_closed_form_every_16th": max(relerr),
+            "difficulty_scale": W.BATCH_SCALE,
             "tile_table": "autotuned" if table else "default"}
 
 
@@ -203,6 +254,9 @@ def main():
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is designed, not built)"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     from paper_2511_01573_amd import gm, workloads as W
 
@@ -247,7 +301,7 @@ def main():
         "regions_per_s": regions / wall,
         "roofline": {"bound": "alu", "kernel": "rule (FP64 vector)", "achieved": achieved,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
                      "rule_kernel_s": rule_s, "rule_launches": launches,
                      "rule_avg_launch_ms": rule_s / launches * 1e3,
                      "rule_evals_per_s": evals / rule_s},
@@ -257,7 +311,7 @@ def main():
     if not args.no_modes:
         sys.path.insert(0, os.path.join(ROOT, "tests"))
         import closed_forms
-        out["batch"] = bench_batch(gm, W, closed_forms, args.batch_sample)
+        out["batch"] = bench_batch(gm, W, closed_forms)
         out["grad"] = bench_grad(gm, W, closed_forms, args.grad_tau, 1 << args.grad_log2cap)
         out["config3"] = bench_config3(gm, W, closed_forms, args.config3_log2cap)
     if not args.no_cpu_baseline:

@@ -198,11 +198,14 @@ int64_t gm_num_nodes(int d);
 /*
  * gm_last_active -- copy out the last evaluated active set of the most recent
  * gm_integrate / gm_integrate_grad call (introspection for parity checks).
- * Copies min(n, count) regions; c, h host double[n*d] row-major, lvl int32[n],
- * q, err double[n], axis int32[n]; any pointer may be NULL.  Returns the count.
+ * Copies regions [offset, offset + n) clipped to the set: c, h host
+ * double[n*d] row-major, lvl int32[n], q, err double[n], axis int32[n] (the
+ * packed byte: bits 0-5 split axis, bit 6 non-finite, bit 7 geometry guard);
+ * any pointer may be NULL.  Returns the count of the whole set (0 when no run
+ * is recorded), GM_EINVAL for offset < 0, GM_EHIP if a copy fails.
  */
-int64_t gm_last_active(int64_t n, double* c, double* h, int32_t* lvl, double* q, double* err,
-                       int32_t* axis);
+int64_t gm_last_active(int64_t offset, int64_t n, double* c, double* h, int32_t* lvl, double* q,
+                       double* err, int32_t* axis);
 
 #ifdef __cplusplus
 }

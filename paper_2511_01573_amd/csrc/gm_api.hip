@@ -948,45 +948,49 @@ int gm_eval_regions(int integrand_id, const double* params, int d, const double*
   return GM_OK;
 }
 
-int64_t gm_last_active(int64_t n, double* c, double* h, int32_t* lvl, double* q, double* err,
-                       int32_t* axis) {
+int64_t gm_last_active(int64_t offset, int64_t n, double* c, double* h, int32_t* lvl, double* q,
+                       double* err, int32_t* axis) {
   std::lock_guard<std::mutex> lk(api_mutex());
   if (!g_last.valid) return 0;
+  if (offset < 0) return GM_EINVAL;
   char* base = g_ext_ptr ? (char*)g_ext_ptr : (char*)g_own_ptr;
-  const int64_t cnt = std::min<int64_t>(n, g_last.n);
+  const int64_t cnt = std::min<int64_t>(n, g_last.n - offset);
   const int d = g_last.d;
   const int b = g_last.buf;
   const Layout& L = g_last.lay;
   if (cnt <= 0) return g_last.n;
+  const size_t o8 = sizeof(double) * (size_t)offset;
   std::vector<double> buf((size_t)cnt);
   for (int j = 0; j < d; ++j) {
     if (c) {
-      if (hipMemcpy(buf.data(), base + L.C[b] + sizeof(double) * j * g_last.cap,
+      if (hipMemcpy(buf.data(), base + L.C[b] + sizeof(double) * j * g_last.cap + o8,
                     sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
-        return -1;
+        return hip_fail(hipGetLastError());
       for (int64_t r = 0; r < cnt; ++r) c[r * d + j] = buf[r];
     }
     if (h) {
-      if (hipMemcpy(buf.data(), base + L.H[b] + sizeof(double) * j * g_last.cap,
+      if (hipMemcpy(buf.data(), base + L.H[b] + sizeof(double) * j * g_last.cap + o8,
                     sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
-        return -1;
+        return hip_fail(hipGetLastError());
       for (int64_t r = 0; r < cnt; ++r) h[r * d + j] = buf[r];
     }
   }
   if (lvl) {
     std::vector<uint16_t> l((size_t)cnt);
-    if (hipMemcpy(l.data(), base + L.L[b], sizeof(uint16_t) * cnt, hipMemcpyDeviceToHost) !=
-        hipSuccess)
-      return -1;
+    if (hipMemcpy(l.data(), base + L.L[b] + sizeof(uint16_t) * offset, sizeof(uint16_t) * cnt,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return hip_fail(hipGetLastError());
     for (int64_t r = 0; r < cnt; ++r) lvl[r] = l[r];
   }
-  if (q && hipMemcpy(q, base + L.Q, sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
-    return -1;
-  if (err && hipMemcpy(err, base + L.ERR, sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
-    return -1;
+  if (q && hipMemcpy(q, base + L.Q + o8, sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
+    return hip_fail(hipGetLastError());
+  if (err &&
+      hipMemcpy(err, base + L.ERR + o8, sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
+    return hip_fail(hipGetLastError());
   if (axis) {
     std::vector<uint8_t> a((size_t)cnt);
-    if (hipMemcpy(a.data(), base + L.AXIS, cnt, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    if (hipMemcpy(a.data(), base + L.AXIS + offset, cnt, hipMemcpyDeviceToHost) != hipSuccess)
+      return hip_fail(hipGetLastError());
     for (int64_t r = 0; r < cnt; ++r) axis[r] = a[r];
   }
   return g_last.n;

@@ -8,14 +8,22 @@
 // contiguous segment inside it, laid out exactly as its own independent run
 // would lay it out (children "-" then children "+", stable order).
 //
+// Every segment is cut into chunks of kChunk regions (a chunk never spans
+// two items), so a large item is reduced and classified by many workgroups
+// instead of one wavefront.
+//
 // One iteration (a fixed launch sequence, replayed from a hipGraph):
-//   rule     one launch per (d, family) group, the group range read on the
-//            device (tile shape per group from the tuning table)
-//   item     one wavefront per item: I, E, T and the stopping rule over its
-//            segment, then the classifier with wave-ballot ranks
-//   commit   one workgroup: shared-capacity check, commit of retired sums,
-//            new segment offsets (exclusive scan over items), group ranges
-//   scatter  halve every kept region into the other buffer
+//   rule      one launch per (d, family) group, the group range read on the
+//             device (tile shape per group from the tuning table)
+//   reduce    one workgroup per chunk: double-double sums of Q and err
+//   finalize  one wavefront per item: I, E over its chunks, T, stopping rule
+//   classify  one workgroup per chunk: retire test, in-chunk ballot ranks,
+//             kept count and retired sums
+//   scan      one wavefront per item: chunk offsets of the kept regions,
+//             retired sums, precision-limit stop
+//   commit    one workgroup: shared-capacity check, commit of retired sums,
+//             new segment offsets and chunk bases (scans over items)
+//   scatter   halve every kept region into the other buffer
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +42,9 @@
 namespace gm {
 
 constexpr int kBatchMaxDim = kTprMaxDim;  // batch items have 2 <= d <= 10
+constexpr int kChunk = 1024;              // regions per chunk = threads per chunk workgroup
+constexpr int kChunkGrid = 2048;          // grid-stride workgroups of the chunk kernels
+constexpr int kMaxBatchItems = 65536;     // item slots the workspace is sized for
 
 struct ItemState {
   int64_t off;     // segment start in the current buffer
@@ -45,6 +56,8 @@ struct ItemState {
   int32_t d;
   int32_t pad;
   int64_t regions;  // regions evaluated for this item
+  int64_t off_prev;    // segment start in the buffer being split (scatter)
+  int64_t cbase_prev;  // first chunk of that segment
   double I, E, T;
   double rel_tol, abs_tol;
   double ifin_hi, ifin_lo, efin_hi, efin_lo;
@@ -53,6 +66,7 @@ struct ItemState {
 
 struct BatchStatus {
   int64_t n_total;    // regions in the current buffer
+  int64_t n_chunks;   // chunks in the current buffer
   int64_t n_prev;     // regions in the buffer being split
   int64_t n_running;  // items still iterating
   int64_t iter;
@@ -78,10 +92,56 @@ struct BatchArgs {
   const double* Q;
   const double* ERR;
   const uint8_t* AXIS;
-  int32_t* RANK;  // keep rank inside the item, -1 = retired
+  int32_t* RANK;  // keep rank inside the chunk, -1 = retired
+  int64_t* ICB;   // first chunk of each item's segment
+  struct ChunkSums* CS;
   int64_t cap;
   int dmax;
 };
+
+// Per-chunk partial results (written by reduce / classify / scan).
+struct ChunkSums {
+  double q_hi, q_lo, e_hi, e_lo;  // sums of Q and err
+  double rq_hi, rq_lo, re_hi, re_lo;  // sums over retired regions
+  int64_t koff;  // offset of this chunk's first kept region inside the item
+  int32_t kept;
+  int32_t nonfinite;
+};
+
+// Item owning chunk c: the last item whose first chunk is <= c (items with no
+// chunks share their successor's base, so the owner is always the last one).
+__device__ __forceinline__ int chunk_item(const BatchArgs& A, int64_t c) {
+  int lo = 0, hi = A.nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.ICB[mid] <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Double-double and integer sums over a workgroup of kChunk threads; the
+// result is valid in thread 0.
+__device__ __forceinline__ void block_sum_chunk(dd& a, dd& b, int& k, dd* sa, dd* sb, int* sk) {
+  a = wave_sum_dd(a);
+  b = wave_sum_dd(b);
+  k = (int)wave_sum_i64(k);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sa[w] = a;
+    sb[w] = b;
+    sk[w] = k;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 1; v < kChunk / 64; ++v) {
+      a = dd_sum(a, sa[v]);
+      b = dd_sum(b, sb[v]);
+      k += sk[v];
+    }
+  }
+  __syncthreads();
+}
 
 // ---------------------------------------------------------------------------
 __global__ void batch_init_kernel(BatchArgs A, const int64_t* item_off0, const int32_t* item_m,
@@ -111,25 +171,56 @@ __global__ void batch_init_kernel(BatchArgs A, const int64_t* item_off0, const i
   }
 }
 
-// One wavefront per item: global sums, stopping rule, classifier.
-__global__ __launch_bounds__(256) void batch_item_kernel(BatchArgs A) {
+// Sums of Q and err over each chunk.
+__global__ __launch_bounds__(kChunk) void batch_reduce_kernel(BatchArgs A) {
+  if (A.bst->n_running == 0) return;
+  __shared__ dd sa[kChunk / 64], sb[kChunk / 64];
+  __shared__ int sk[kChunk / 64];
+  const int64_t nc = A.bst->n_chunks;
+  for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int it = chunk_item(A, c);
+    const ItemState& S = A.items[it];
+    const int64_t k0 = S.off + (c - A.ICB[it]) * kChunk;
+    const int64_t k1 = min(S.off + S.n, k0 + kChunk);
+    const int64_t r = k0 + threadIdx.x;
+    dd q = {0.0, 0.0}, e = {0.0, 0.0};
+    int nf = 0;
+    if (r < k1) {
+      q.hi = A.Q[r];
+      e.hi = A.ERR[r];
+      nf = (A.AXIS[r] & kNonfiniteBit) ? 1 : 0;
+    }
+    block_sum_chunk(q, e, nf, sa, sb, sk);
+    if (threadIdx.x == 0) {
+      ChunkSums& C = A.CS[c];
+      C.q_hi = q.hi;
+      C.q_lo = q.lo;
+      C.e_hi = e.hi;
+      C.e_lo = e.lo;
+      C.nonfinite = nf;
+    }
+  }
+}
+
+// One wavefront per item: I and E over its chunks, T, the stopping rule.
+__global__ __launch_bounds__(256) void batch_finalize_kernel(BatchArgs A) {
   const int lane = threadIdx.x & 63;
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nw = (gridDim.x * blockDim.x) >> 6;
   if (A.bst->n_running == 0) return;
-  const int buf = A.bst->buf;
-  const uint16_t* __restrict__ Lb = A.L[buf];
   const int64_t max_iters = A.bst->max_iters;
   for (int it = wid; it < A.nitems; it += nw) {
     ItemState& S = A.items[it];
     if (S.done) continue;
-    const int64_t off = S.off, n = S.n;
+    const int64_t cb = A.ICB[it];
+    const int64_t nch = (S.n + kChunk - 1) / kChunk;
     dd q = {0.0, 0.0}, e = {0.0, 0.0};
     int nonfin = 0;
-    for (int64_t k = lane; k < n; k += 64) {
-      dd_add(q, A.Q[off + k]);
-      dd_add(e, A.ERR[off + k]);
-      nonfin |= (A.AXIS[off + k] & kNonfiniteBit) ? 1 : 0;
+    for (int64_t k = lane; k < nch; k += 64) {
+      const ChunkSums& C = A.CS[cb + k];
+      q = dd_sum(q, dd{C.q_hi, C.q_lo});
+      e = dd_sum(e, dd{C.e_hi, C.e_lo});
+      nonfin |= C.nonfinite;
     }
     q = wave_sum_dd(q);
     e = wave_sum_dd(e);
@@ -147,44 +238,113 @@ __global__ __launch_bounds__(256) void batch_item_kernel(BatchArgs A) {
       if (E <= T) status = GM_OK;
       else if (iter >= max_iters) status = GM_MAX_ITERS;
     }
-    int64_t nk = 0;
-    dd fq = {0.0, 0.0}, fe = {0.0, 0.0};
-    if (status < 0) {
-      const double aI = fabs(I);
-      for (int64_t k0 = 0; k0 < n; k0 += 64) {
-        const int64_t k = k0 + lane;
-        bool keep = false;
-        if (k < n) {
-          const double err = A.ERR[off + k];
-          const bool fin = (err <= ldexp(T, -(int)Lb[off + k])) || (aI + err == aI) ||
-                           (A.AXIS[off + k] & kGeoBit);
-          keep = !fin;
-          if (fin) {
-            dd_add(fq, A.Q[off + k]);
-            dd_add(fe, err);
-          }
-        }
-        const uint64_t mask = __ballot(keep);
-        if (k < n) A.RANK[off + k] = keep ? (int32_t)(nk + __popcll(mask & ((1ull << lane) - 1ull))) : -1;
-        nk += __popcll(mask);
-      }
-      fq = wave_sum_dd(fq);
-      fe = wave_sum_dd(fe);
-      if (nk == 0) status = GM_PRECISION_LIMIT;
-    }
     if (lane == 0) {
-      S.regions += n;
+      S.regions += S.n;
       S.iter = iter;
       S.I = nonfin ? NAN : I;
       S.E = nonfin ? NAN : E;
       S.T = T;
-      S.nk = nk;
+      S.nk = 0;
+      if (status >= 0) {
+        S.status = status;
+        S.done = 1;
+      }
+    }
+  }
+}
+
+// Classifier over each chunk of the running items: retire test, stable
+// in-chunk ranks of the kept regions, kept count and retired sums.
+__global__ __launch_bounds__(kChunk) void batch_classify_kernel(BatchArgs A) {
+  if (A.bst->n_running == 0) return;
+  __shared__ dd sa[kChunk / 64], sb[kChunk / 64];
+  __shared__ int sk[kChunk / 64];
+  __shared__ int wkeep[kChunk / 64];
+  const int buf = A.bst->buf;
+  const uint16_t* __restrict__ Lb = A.L[buf];
+  const int64_t nc = A.bst->n_chunks;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    const int it = chunk_item(A, c);
+    const ItemState& S = A.items[it];
+    if (S.done) continue;  // the same item for the whole workgroup
+    const int64_t k0 = S.off + (c - A.ICB[it]) * kChunk;
+    const int64_t k1 = min(S.off + S.n, k0 + kChunk);
+    const int64_t r = k0 + threadIdx.x;
+    const double T = S.T, aI = fabs(S.I);
+    bool keep = false;
+    dd fq = {0.0, 0.0}, fe = {0.0, 0.0};
+    if (r < k1) {
+      const double err = A.ERR[r];
+      const bool fin = (err <= ldexp(T, -(int)Lb[r])) || (aI + err == aI) ||
+                       (A.AXIS[r] & kGeoBit);
+      keep = !fin;
+      if (fin) {
+        fq.hi = A.Q[r];
+        fe.hi = err;
+      }
+    }
+    const uint64_t mask = __ballot(keep);
+    if (lane == 0) wkeep[w] = __popcll(mask);
+    __syncthreads();
+    int before = 0;
+    for (int v = 0; v < w; ++v) before += wkeep[v];
+    if (r < k1) A.RANK[r] = keep ? before + __popcll(mask & ((1ull << lane) - 1ull)) : -1;
+    int kept = keep ? 1 : 0;
+    block_sum_chunk(fq, fe, kept, sa, sb, sk);
+    if (threadIdx.x == 0) {
+      ChunkSums& C = A.CS[c];
+      C.rq_hi = fq.hi;
+      C.rq_lo = fq.lo;
+      C.re_hi = fe.hi;
+      C.re_lo = fe.lo;
+      C.kept = kept;
+    }
+  }
+}
+
+// One wavefront per running item: offsets of its chunks' kept regions,
+// kept total, retired sums; no kept region left = precision limit.
+__global__ __launch_bounds__(256) void batch_scan_kernel(BatchArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  if (A.bst->n_running == 0) return;
+  for (int it = wid; it < A.nitems; it += nw) {
+    ItemState& S = A.items[it];
+    if (S.done) continue;
+    const int64_t cb = A.ICB[it];
+    const int64_t nch = (S.n + kChunk - 1) / kChunk;
+    int64_t run = 0;
+    dd fq = {0.0, 0.0}, fe = {0.0, 0.0};
+    for (int64_t k0 = 0; k0 < nch; k0 += 64) {
+      const int64_t k = k0 + lane;
+      int64_t kept = 0;
+      if (k < nch) {
+        ChunkSums& C = A.CS[cb + k];
+        kept = C.kept;
+        fq = dd_sum(fq, dd{C.rq_hi, C.rq_lo});
+        fe = dd_sum(fe, dd{C.re_hi, C.re_lo});
+      }
+      int64_t inc = kept;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+      }
+      if (k < nch) A.CS[cb + k].koff = run + inc - kept;
+      run += __shfl(inc, 63, 64);
+    }
+    fq = wave_sum_dd(fq);
+    fe = wave_sum_dd(fe);
+    if (lane == 0) {
+      S.nk = run;
       S.pq_hi = fq.hi;
       S.pq_lo = fq.lo;
       S.pe_hi = fe.hi;
       S.pe_lo = fe.lo;
-      if (status >= 0) {
-        S.status = status;
+      if (run == 0) {
+        S.status = GM_PRECISION_LIMIT;
         S.done = 1;
       }
     }
@@ -199,30 +359,42 @@ __global__ __launch_bounds__(1024) void batch_commit_kernel(BatchArgs A) {
   const int per = (nit + 1023) / 1024;
   const int i0 = threadIdx.x * per;
   const int i1 = min(nit, i0 + per);
-  int64_t need = 0, running = 0;
+  int64_t need = 0, running = 0, chunks = 0;
   for (int i = i0; i < i1; ++i)
     if (!A.items[i].done) {
       need += 2 * A.items[i].nk;
+      chunks += (2 * A.items[i].nk + kChunk - 1) / kChunk;
       running += 1;
     }
-  // block reductions / scan
+  // block reductions / scans (regions and chunks)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int64_t inc = need;
+  int64_t inc = need, cinc = chunks;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const int64_t y = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += y;
+    const int64_t yc = __shfl_up(cinc, o, 64);
+    if (lane >= o) {
+      inc += y;
+      cinc += yc;
+    }
   }
-  __shared__ int64_t wt[16], wr[16];
+  __shared__ int64_t wt[16], wr[16], wc[16];
   __shared__ int over;
   const int64_t rsum = wave_sum_i64(running);
-  if (lane == 63) wt[w] = inc;
+  if (lane == 63) {
+    wt[w] = inc;
+    wc[w] = cinc;
+  }
   if (lane == 0) wr[w] = rsum;
   __syncthreads();
-  int64_t woff = 0, total = 0, nrun = 0;
+  int64_t woff = 0, total = 0, nrun = 0, cwoff = 0, ctotal = 0;
   for (int k = 0; k < 16; ++k) {
-    if (k < w) woff += wt[k];
+    if (k < w) {
+      woff += wt[k];
+      cwoff += wc[k];
+    }
     total += wt[k];
+    ctotal += wc[k];
     nrun += wr[k];
   }
   if (threadIdx.x == 0) over = (total > B->cap) ? 1 : 0;
@@ -249,8 +421,12 @@ __global__ __launch_bounds__(1024) void batch_commit_kernel(BatchArgs A) {
     return;
   }
   int64_t run = woff + inc - need;
+  int64_t crun = cwoff + cinc - chunks;
   for (int i = i0; i < i1; ++i) {
     ItemState& S = A.items[i];
+    S.off_prev = S.off;
+    S.cbase_prev = A.ICB[i];
+    A.ICB[i] = crun;
     if (!S.done) {
       const dd fi = dd_sum(dd{S.ifin_hi, S.ifin_lo}, dd{S.pq_hi, S.pq_lo});
       const dd fe = dd_sum(dd{S.efin_hi, S.efin_lo}, dd{S.pe_hi, S.pe_lo});
@@ -261,6 +437,7 @@ __global__ __launch_bounds__(1024) void batch_commit_kernel(BatchArgs A) {
       S.off = run;
       S.n = 2 * S.nk;
       run += 2 * S.nk;
+      crun += (2 * S.nk + kChunk - 1) / kChunk;
     } else {
       S.off = run;
       S.n = 0;
@@ -278,6 +455,7 @@ __global__ __launch_bounds__(1024) void batch_commit_kernel(BatchArgs A) {
     B->n_prev = B->n_total;
     B->n_running = nrun;
     B->n_total = total;
+    B->n_chunks = ctotal;
     B->iter += 1;
     B->buf = 1 - B->buf;
   }
@@ -298,7 +476,9 @@ __global__ __launch_bounds__(256) void batch_scatter_kernel(BatchArgs A) {
     if (S.done) continue;
     const int32_t p = A.RANK[r];
     if (p < 0) continue;
-    const int64_t p0 = S.off + p, p1 = S.off + S.nk + p;
+    const int64_t c = S.cbase_prev + (r - S.off_prev) / kChunk;
+    const int64_t pk = A.CS[c].koff + p;
+    const int64_t p0 = S.off + pk, p1 = S.off + S.nk + pk;
     const int ax = A.AXIS[r] & kAxisMask;
     for (int j = 0; j < S.d; ++j) {
       const double cj = A.C[in][j * cap + r];
@@ -342,8 +522,8 @@ std::map<int, Tile>& tile_table() {
 int tile_key(int d, int fam) { return d * 16 + fam; }
 
 struct BatchLayout {
-  size_t C[2], H[2], L[2], IT[2], Q, ERR, AXIS, RANK;
-  size_t items, params, vol, gfirst, glast, grange, bst, off0, m, lo, half;
+  size_t C[2], H[2], L[2], IT[2], Q, ERR, AXIS, RANK, CS;
+  size_t items, icb, params, vol, gfirst, glast, grange, bst, off0, m, lo, half;
   size_t total;
 };
 
@@ -365,7 +545,9 @@ BatchLayout batch_layout(int dmax, int64_t cap, int nv, int ng) {
   B.ERR = take(sizeof(double) * cap);
   B.AXIS = take(cap);
   B.RANK = take(sizeof(int32_t) * cap);
+  B.CS = take(sizeof(ChunkSums) * (size_t)(cap / kChunk + nv + 1));
   B.items = take(sizeof(ItemState) * nv);
+  B.icb = take(sizeof(int64_t) * nv);
   B.params = take(sizeof(DevParams) * nv);
   B.vol = take(sizeof(double) * nv);
   B.gfirst = take(sizeof(int32_t) * ng);
@@ -389,8 +571,8 @@ struct BatchNode {
 }  // namespace
 
 size_t batch_layout_bytes(int dmax, int64_t cap) {
-  // per-item state for up to 65536 items and 64 groups
-  return batch_layout(dmax, cap, 65536, 64).total;
+  // per-item state for up to kMaxBatchItems items and 64 groups
+  return batch_layout(dmax, cap, kMaxBatchItems, 64).total;
 }
 
 int set_tile(int d, int fam, int lanes, int grid) {
@@ -497,6 +679,12 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
     n0 += items[k].n;
   }
   if (n0 > cap) return GM_EINVAL;
+  std::vector<int64_t> icb(nv);
+  int64_t nchunks0 = 0;
+  for (int k = 0; k < nv; ++k) {
+    icb[k] = nchunks0;
+    nchunks0 += (items[k].n + kChunk - 1) / kChunk;
+  }
   std::vector<int64_t> grange(2 * ng);
   for (int g = 0; g < ng; ++g) {
     grange[2 * g] = items[gfirst[g]].off;
@@ -509,6 +697,7 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
   BatchStatus hb;
   std::memset(&hb, 0, sizeof hb);
   hb.n_total = n0;
+  hb.n_chunks = nchunks0;
   hb.n_running = nv;
   hb.cap = cap;
   hb.max_iters = opt.max_iters;
@@ -517,6 +706,7 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
   };
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = up(lay.items, items.data(), sizeof(ItemState) * nv);
+  if (e == hipSuccess) e = up(lay.icb, icb.data(), sizeof(int64_t) * nv);
   if (e == hipSuccess) e = up(lay.params, dparams.data(), sizeof(DevParams) * nv);
   if (e == hipSuccess) e = up(lay.vol, vol.data(), sizeof(double) * nv);
   if (e == hipSuccess) e = up(lay.gfirst, gfirst.data(), sizeof(int32_t) * ng);
@@ -548,6 +738,8 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
   A.ERR = (const double*)(base + lay.ERR);
   A.AXIS = (const uint8_t*)(base + lay.AXIS);
   A.RANK = (int32_t*)(base + lay.RANK);
+  A.ICB = (int64_t*)(base + lay.icb);
+  A.CS = (ChunkSums*)(base + lay.CS);
   A.cap = cap;
   A.dmax = dmax;
   {
@@ -594,7 +786,10 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
     for (int g = 0; g < ng; ++g) {
       hipLaunchKernelGGL(rfn[g], dim3(rgrid[g]), dim3(kRuleBlockSize), 0, s, rargs[g]);
     }
-    hipLaunchKernelGGL(batch_item_kernel, dim3(item_grid), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(kChunkGrid), dim3(kChunk), 0, s, A);
+    hipLaunchKernelGGL(batch_finalize_kernel, dim3(item_grid), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(batch_classify_kernel, dim3(kChunkGrid), dim3(kChunk), 0, s, A);
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(item_grid), dim3(256), 0, s, A);
     hipLaunchKernelGGL(batch_commit_kernel, dim3(1), dim3(1024), 0, s, A);
     hipLaunchKernelGGL(batch_scatter_kernel, dim3(scat_grid), dim3(256), 0, s, A);
     return hipGetLastError();
@@ -634,11 +829,18 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
         p.kernelParams = args;
         return hipGraphAddKernelNode(node, graph, dep.data(), dep.size(), &p);
       };
-      hipGraphNode_t n_item, n_commit, n_scatter;
+      hipGraphNode_t n_red = nullptr, n_fin = nullptr, n_cls = nullptr, n_scan = nullptr,
+                     n_commit = nullptr, n_scatter = nullptr;
       if (e == hipSuccess)
-        e = add((void*)batch_item_kernel, dim3(item_grid), dim3(256), rules, &n_item);
+        e = add((void*)batch_reduce_kernel, dim3(kChunkGrid), dim3(kChunk), rules, &n_red);
       if (e == hipSuccess)
-        e = add((void*)batch_commit_kernel, dim3(1), dim3(1024), {n_item}, &n_commit);
+        e = add((void*)batch_finalize_kernel, dim3(item_grid), dim3(256), {n_red}, &n_fin);
+      if (e == hipSuccess)
+        e = add((void*)batch_classify_kernel, dim3(kChunkGrid), dim3(kChunk), {n_fin}, &n_cls);
+      if (e == hipSuccess)
+        e = add((void*)batch_scan_kernel, dim3(item_grid), dim3(256), {n_cls}, &n_scan);
+      if (e == hipSuccess)
+        e = add((void*)batch_commit_kernel, dim3(1), dim3(1024), {n_scan}, &n_commit);
       if (e == hipSuccess)
         e = add((void*)batch_scatter_kernel, dim3(scat_grid), dim3(256), {n_commit}, &n_scatter);
       prev = {n_scatter};

@@ -95,8 +95,17 @@ GM_HD double cos(double x) {
   const double hi = fma(z, -0.5, 1.0);
   const double lo = fma(-rh, rl, fma(z, -0.5, 1.0 - hi));
   const double c = hi + fma(z * z, q, lo);
-  // cos(r + k pi) = (-1)^k cos r
-  return (k & 1) ? -c : c;
+  // cos(r + k pi) = (-1)^k cos r: bit 0 of k moved into the sign bit
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __hiloint2double(__double2hiint(c) ^ (int)((uint32_t)k << 31), __double2loint(c));
+#else
+  uint32_t w[2];
+  std::memcpy(w, &c, sizeof w);
+  w[1] ^= (uint32_t)k << 31;
+  double out;
+  std::memcpy(&out, w, sizeof out);
+  return out;
+#endif
 }
 
 // 1/x: the hardware reciprocal estimate refined by two Newton steps

@@ -43,6 +43,7 @@ constexpr int kRuleBlock = kRuleBlockSize;
 #endif
 
 
+
 // ---------------------------------------------------------------------------
 // Family traits: term, combination and outer function (Sec. 4 integrands).
 // ---------------------------------------------------------------------------
@@ -346,22 +347,24 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
       for (int k = i + 1; k < D; ++k) s = F::comb(s, tc[k]);
       f[q] = F::template outer<D>(P, s);
     }
-    ks_add(S2, f[0]);
-    ks_add(S2, f[1]);
-    ks_add(S3, f[2]);
-    ks_add(S3, f[3]);
+    ks_add(S2, f[0] + f[1]);
+    ks_add(S3, f[2] + f[3]);
     double sc;
     fourth_diff(K, f0, f[0], f[1], f[2], f[3], Dv[i], sc);
     scale = sc > scale ? sc : scale;
   }
   // Class 4 walks (i, j) with loop counters that are the same in every lane
-  // of the wavefront, so the term arrays are indexed uniformly.
+  // of the wavefront, so the term arrays are indexed uniformly.  Class sums
+  // are compensated at the level of small groups: the +-pair of each class 2/3
+  // axis and the (at most 2(d-1)) nodes of one (i, sign_i) row of class 4 are
+  // added plainly and each group sum enters the compensated total.
 #pragma unroll GM_UNROLL_A4
   for (int i = 0; i < D - 1; ++i) {
 #pragma unroll
     for (int si = 0; si < 2; ++si) {
       const double ti = si ? t3m[i] : t3p[i];
       double m = (i == 0) ? ti : F::comb(pc[i], ti);
+      double g = 0.0;
 #pragma unroll GM_UNROLL_A4
       for (int j = i + 1; j < D; ++j) {
 #pragma unroll
@@ -369,10 +372,12 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
           double s = F::comb(m, sj ? t3m[j] : t3p[j]);
 #pragma unroll GM_UNROLL_A4
           for (int k = j + 1; k < D; ++k) s = F::comb(s, tc[k]);
-          ks_add(S4, F::template outer<D>(P, s));
+          const double fv = F::template outer<D>(P, s);
+          g = (j == i + 1 && sj == 0) ? fv : g + fv;
         }
         m = F::comb(m, tc[j]);
       }
+      ks_add(S4, g);
     }
   }
   {
@@ -413,8 +418,13 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
   return r;
 }
 
+// Two wavefronts per SIMD: the compiler keeps the register file at 256 per
+// lane (a few phase-A values spill to scratch, none inside the corner loop) so
+// a second wavefront hides the latency of the first one's dependent FP64
+// chains and loads.
 template <int D, int FAM, bool BATCH>
-__global__ __launch_bounds__(kRuleBlock) void rule_tpr_kernel(RuleArgs A) {
+__global__ __launch_bounds__(kRuleBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void rule_tpr_kernel(RuleArgs A) {
   int64_t start, end;
   int buf;
   if (!active_range<BATCH>(A, start, end, buf)) return;
@@ -422,19 +432,21 @@ __global__ __launch_bounds__(kRuleBlock) void rule_tpr_kernel(RuleArgs A) {
   const double* __restrict__ Hb = A.H[buf];
   const uint16_t* __restrict__ Lb = A.L[buf];
   const int64_t cap = A.cap;
+  const int64_t stride = (int64_t)gridDim.x * kRuleBlock;
   dd qs = {0.0, 0.0}, es = {0.0, 0.0};
   int nonfin = 0;
-  for (int64_t r = start + (int64_t)blockIdx.x * kRuleBlock + threadIdx.x; r < end;
-       r += (int64_t)gridDim.x * kRuleBlock) {
+  int64_t r = start + (int64_t)blockIdx.x * kRuleBlock + threadIdx.x;
+  for (; r < end; r += stride) {
     double c[D], h[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       c[j] = Cb[j * cap + r];
       h[j] = Hb[j * cap + r];
     }
+    const int lvl = Lb[r];
     double volo;
     const DevParams& P = region_params<BATCH>(A, buf, r, volo);
-    const double vol = ldexp(volo, -(int)Lb[r]);
+    const double vol = ldexp(volo, -lvl);
     const RegionResult o = rule_region_tpr<D, FAM>(P, A.K, c, h, vol);
     store_result(A, r, o);
     dd_add(qs, o.q);

@@ -98,7 +98,7 @@ def lib():
         L.gm_set_tile.restype = C.c_int
         L.gm_set_tile.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.gm_last_active.restype = C.c_int64
-        L.gm_last_active.argtypes = [C.c_int64, dp, dp, i32p, dp, dp, i32p]
+        L.gm_last_active.argtypes = [C.c_int64, C.c_int64, dp, dp, i32p, dp, dp, i32p]
         _lib = L
     return _lib
 
@@ -248,10 +248,17 @@ def eval_regions(family, params, lo, hi, c, h, lvl, stream=None):
     return q, e, ax
 
 
-def last_active(d: int):
-    """The last evaluated active set of the previous integrate call."""
+def last_active_count() -> int:
+    """Size of the last evaluated active set of the previous integrate call."""
+    return int(lib().gm_last_active(0, 0, None, None, None, None, None, None))
+
+
+def last_active(d: int, offset: int = 0, count: int | None = None):
+    """Regions [offset, offset + count) of the last evaluated active set of the
+    previous integrate call (the whole set by default)."""
     L = lib()
-    n = int(L.gm_last_active(0, None, None, None, None, None, None))
+    total = last_active_count()
+    n = max(0, min(total - offset, total if count is None else count))
     c = np.zeros((n, d))
     h = np.zeros((n, d))
     lvl = np.zeros(n, dtype=np.int32)
@@ -260,8 +267,9 @@ def last_active(d: int):
     ax = np.zeros(n, dtype=np.int32)
     P = C.POINTER(C.c_double)
     I32 = C.POINTER(C.c_int32)
-    got = L.gm_last_active(n, c.ctypes.data_as(P), h.ctypes.data_as(P), lvl.ctypes.data_as(I32),
-                           q.ctypes.data_as(P), e.ctypes.data_as(P), ax.ctypes.data_as(I32))
+    got = L.gm_last_active(offset, n, c.ctypes.data_as(P), h.ctypes.data_as(P),
+                           lvl.ctypes.data_as(I32), q.ctypes.data_as(P), e.ctypes.data_as(P),
+                           ax.ctypes.data_as(I32))
     if got < 0:
-        raise GMError(EHIP, "gm_last_active copy failed")
+        _check(int(got))
     return {"c": c, "h": h, "lvl": lvl, "Q": q, "err": e, "axis": ax}

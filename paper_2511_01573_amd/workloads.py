@@ -21,6 +21,11 @@ NAMES = {1: "oscillatory", 2: "product_peak", 3: "corner_peak", 4: "gaussian", 5
 # then frozen (input recipe).
 DIFFICULTY_D8 = {OSCILLATORY: 9.0, PRODUCT_PEAK: 15.0, CORNER_PEAK: 2.0, GAUSSIAN: 13.0,
                  C0: 4.0, DISCONTINUOUS: 10.0}
+# Batch difficulty: sum(a) = BATCH_SCALE * b_family * d / 8.  At 0.35 each of
+# the 4096 integrals converges on its own below 2^26 regions (at 0.5 five
+# product-peak items at d = 9, 10 and rel_tol < 1e-6 do not) and the
+# lock-step batch fits a shared store of 2^28 regions.
+BATCH_SCALE = 0.35
 # Number of leading coordinates that carry a discontinuity in the seeded
 # discontinuous family; the others get u_j = 1 (no cut inside [0,1]).
 DISC_CUT_DIMS = 2
@@ -78,9 +83,9 @@ def config3(dims=(12, 16), tau=1e-4, max_regions=1 << 26):
     return out
 
 
-def config4(n=4096, seed=4096):
+def config4(n=4096, seed=4096, scale=BATCH_SCALE):
     """Batch: d_i ~ U{3..10}, family ~ U{Gaussian, oscillatory, product peak},
-    a, u seeded, rel_tol_i = 10^U(-7, -3)."""
+    a, u seeded (sum(a) = scale * b_family * d / 8), rel_tol_i = 10^U(-7, -3)."""
     rng = np.random.default_rng(seed)
     fams, params, ds, los, his, rts, ats = [], [], [], [], [], [], []
     choices = [GAUSSIAN, OSCILLATORY, PRODUCT_PEAK]
@@ -89,7 +94,7 @@ def config4(n=4096, seed=4096):
         fam = choices[int(rng.integers(0, 3))]
         a = rng.uniform(0.0, 1.0, d)
         u = rng.uniform(0.0, 1.0, d)
-        a = a * (DIFFICULTY_D8[fam] * d / 8.0 / a.sum())
+        a = a * (scale * DIFFICULTY_D8[fam] * d / 8.0 / a.sum())
         tau = 10.0 ** rng.uniform(-7.0, -3.0)
         fams.append(fam)
         params.append(np.concatenate([a, u]))

@@ -112,7 +112,12 @@ def test_batch_matches_oracle_lockstep(graph_iters):
             I, E, s1 = gm.integrate(b[0][i], b[1][i], b[3][i], b[4][i], b[5][i], 1e-16, 1 << 22)
         finally:
             gm.set_option("init_log2_regions", 12)
-        assert s1 == st[i] and I == est[i] and E == err[i]
+        # the same tree summed in another order (chunked batch reductions, and
+        # at small active counts the single path spreads a region over several
+        # lanes): equal up to the rounding of the sums and of err's cancellation
+        assert s1 == st[i]
+        assert abs(I - est[i]) <= I_TOL * abs(I), (i, I, est[i])
+        assert abs(E - err[i]) <= 1e-9 * E, (i, E, err[i])
 
 
 def test_batch_shared_capacity_and_invalid_items():
