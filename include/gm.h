@@ -154,7 +154,8 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  *   "graph_iters"        iterations per hipGraph replay, 0 = launch kernels
  *                        directly with a host check every iteration (default 0)
  *   "lanes_per_region"   0 = automatic, else 1..64 power of two (rule kernel mapping)
- *   "timing"             1 = record per-phase device time with hipEvents (default 0)
+ *   "timing"             1 = record the rule kernel's device time with hipEvents on
+ *                        the call's stream, 2 = every phase (default 0 = off)
  *   "log"                1 = print one line per iteration to stderr (default 0)
  */
 int gm_set_option(const char* key, int64_t value);
@@ -173,9 +174,9 @@ typedef struct {
   int64_t status;            /* status of the call                                 */
   int64_t lanes_per_region;  /* rule-kernel mapping used in the last iteration      */
   double rule_ms;            /* device time in the rule kernel (option timing)      */
-  double reduce_ms;          /* global reduction + convergence test                 */
-  double classify_ms;        /* classify + block counts                             */
-  double split_ms;           /* scan + split + compaction                           */
+  double reduce_ms;          /* global reduction + convergence test (timing 2)      */
+  double classify_ms;        /* classify + block counts (timing 2)                  */
+  double split_ms;           /* scan + split + compaction (timing 2)                */
   double total_ms;           /* wall time of the call                               */
   int64_t rule_launches;     /* number of rule-kernel launches timed                */
 } gm_stats;

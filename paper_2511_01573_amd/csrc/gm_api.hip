@@ -762,7 +762,8 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   // store grows on the host's side).
   constexpr int kMaxAhead = 8;
   hipEvent_t ev[kMaxAhead][5] = {};
-  const bool timing = g_opt.timing != 0;
+  const bool timing = g_opt.timing != 0;       // rule kernel only
+  const bool phases = g_opt.timing >= 2;       // every phase
   if (timing)
     for (auto& row : ev)
       for (auto& e : row) GM_HIP(hipEventCreate(&e));
@@ -794,15 +795,15 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       if (timing) GM_HIP(hipEventRecord(ev[k][1], s));
       hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, st, ra.partials, rg);
       GM_HIP(hipGetLastError());
-      if (timing) GM_HIP(hipEventRecord(ev[k][2], s));
+      if (phases) GM_HIP(hipEventRecord(ev[k][2], s));
       hipLaunchKernelGGL(classify_kernel, dim3(tg), dim3(kTileThreads), 0, s, ca);
       GM_HIP(hipGetLastError());
-      if (timing) GM_HIP(hipEventRecord(ev[k][3], s));
+      if (phases) GM_HIP(hipEventRecord(ev[k][3], s));
       hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, st, ca.TK, sa.TOFF, ca.TQ, ca.TE);
       GM_HIP(hipGetLastError());
       hipLaunchKernelGGL(scatter_fn(d), dim3(tg), dim3(kTileThreads), 0, s, sa);
       GM_HIP(hipGetLastError());
-      if (timing) GM_HIP(hipEventRecord(ev[k][4], s));
+      if (phases) GM_HIP(hipEventRecord(ev[k][4], s));
       nb = std::min<int64_t>(cap, 2 * nb);
     }
     GM_HIP(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
@@ -813,9 +814,11 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       for (int k = 0; k < ran; ++k) {
         float a = 0, b = 0, c = 0, e = 0;
         GM_HIP(hipEventElapsedTime(&a, ev[k][0], ev[k][1]));
-        GM_HIP(hipEventElapsedTime(&b, ev[k][1], ev[k][2]));
-        GM_HIP(hipEventElapsedTime(&c, ev[k][2], ev[k][3]));
-        GM_HIP(hipEventElapsedTime(&e, ev[k][3], ev[k][4]));
+        if (phases) {
+          GM_HIP(hipEventElapsedTime(&b, ev[k][1], ev[k][2]));
+          GM_HIP(hipEventElapsedTime(&c, ev[k][2], ev[k][3]));
+          GM_HIP(hipEventElapsedTime(&e, ev[k][3], ev[k][4]));
+        }
         g_stats.rule_ms += a;
         g_stats.reduce_ms += b;
         g_stats.classify_ms += c;
@@ -1032,7 +1035,8 @@ int gm_set_option(const char* key, int64_t value) {
     if (value < 0 || value > 64 || (value & (value - 1))) return GM_EINVAL;
     g_opt.lanes_per_region = (int)value;
   } else if (k == "timing") {
-    g_opt.timing = value ? 1 : 0;
+    if (value < 0 || value > 2) return GM_EINVAL;
+    g_opt.timing = (int)value;
   } else if (k == "log") {
     g_opt.log = value ? 1 : 0;
   } else {

@@ -64,48 +64,87 @@ GM_HD int32_t low_word(double t) {
   return (int32_t)(uint32_t)b;
 }
 
-GM_HD double exp(double x) {
-  x = fmax(x, -1100.0);
-  const double t = fma(x, kInvLn2, kShift);
-  const double kd = t - kShift;
-  const int32_t k = low_word(t);
-  double r = fma(-kd, kLn2Hi, x);
-  r = fma(-kd, kLn2Lo, r);
-  double p = kExpPoly[0];
+// N-wide forms: the same operations on N independent arguments, written
+// step by step across the N values so the dependent FMA chains of neighbouring
+// nodes interleave (each element gets exactly the scalar function's result).
+template <int N>
+GM_HD void exp_n(const double (&xin)[N], double (&y)[N]) {
+  double x[N], t[N], kd[N], r[N], p[N];
+  int32_t k[N];
 #pragma unroll
-  for (int i = 1; i < 12; ++i) p = fma(p, r, kExpPoly[i]);
-  return ldexp(p, k);
+  for (int i = 0; i < N; ++i) {
+    x[i] = fmax(xin[i], -1100.0);
+    t[i] = fma(x[i], kInvLn2, kShift);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    kd[i] = t[i] - kShift;
+    k[i] = low_word(t[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = fma(-kd[i], kLn2Hi, x[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = fma(-kd[i], kLn2Lo, r[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) p[i] = kExpPoly[0];
+#pragma unroll
+  for (int c = 1; c < 12; ++c) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = fma(p[i], r[i], kExpPoly[c]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) y[i] = ldexp(p[i], k[i]);
 }
 
-GM_HD double cos(double x) {
-  const double t = fma(x, kInvPi, kShift);
-  const double kd = t - kShift;
-  const int32_t k = low_word(t);
+template <int N>
+GM_HD void cos_n(const double (&x)[N], double (&y)[N]) {
+  double t[N], kd[N], r1[N], rh[N], rl[N], z[N], q[N], hi[N], lo[N], c[N];
+  int32_t k[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    t[i] = fma(x[i], kInvPi, kShift);
+    kd[i] = t[i] - kShift;
+    k[i] = low_word(t[i]);
+  }
   // r = x - k pi as rh + rl: the first step is exact (Cody-Waite), the
   // rounding error of the second is recovered with one more FMA.
-  const double r1 = fma(-kd, kPi_1, x);
-  const double rh = fma(-kd, kPi_2, r1);
-  const double rl = fma(-kd, kPi_3, fma(-kd, kPi_2, r1 - rh));
-  const double z = rh * rh;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r1[i] = fma(-kd[i], kPi_1, x[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) rh[i] = fma(-kd[i], kPi_2, r1[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) rl[i] = fma(-kd[i], kPi_3, fma(-kd[i], kPi_2, r1[i] - rh[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    z[i] = rh[i] * rh[i];
+    q[i] = kCosPoly[0];
+  }
   // cos r = (1 - z/2) + z^2 Q(z) - sin(rh) rl: the leading part is rounded
   // once and its rounding error is carried into the small tail.
-  double q = kCosPoly[0];
 #pragma unroll
-  for (int i = 1; i < 8; ++i) q = fma(q, z, kCosPoly[i]);
-  const double hi = fma(z, -0.5, 1.0);
-  const double lo = fma(-rh, rl, fma(z, -0.5, 1.0 - hi));
-  const double c = hi + fma(z * z, q, lo);
+  for (int cc = 1; cc < 8; ++cc) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) q[i] = fma(q[i], z[i], kCosPoly[cc]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    hi[i] = fma(z[i], -0.5, 1.0);
+    lo[i] = fma(-rh[i], rl[i], fma(z[i], -0.5, 1.0 - hi[i]));
+    c[i] = hi[i] + fma(z[i] * z[i], q[i], lo[i]);
+  }
   // cos(r + k pi) = (-1)^k cos r: bit 0 of k moved into the sign bit
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  return __hiloint2double(__double2hiint(c) ^ (int)((uint32_t)k << 31), __double2loint(c));
+    y[i] = __hiloint2double(__double2hiint(c[i]) ^ (int)((uint32_t)k[i] << 31),
+                            __double2loint(c[i]));
 #else
-  uint32_t w[2];
-  std::memcpy(w, &c, sizeof w);
-  w[1] ^= (uint32_t)k << 31;
-  double out;
-  std::memcpy(&out, w, sizeof out);
-  return out;
+    uint32_t w[2];
+    std::memcpy(w, &c[i], sizeof w);
+    w[1] ^= (uint32_t)k[i] << 31;
+    std::memcpy(&y[i], w, sizeof w);
 #endif
+  }
 }
 
 // 1/x: the hardware reciprocal estimate refined by two Newton steps
@@ -113,17 +152,46 @@ GM_HD double cos(double x) {
 // for |x| in [2^-1022, 2^1022].  Outside that range (reciprocals beyond the
 // normal range) the result may flush to 0 or be non-finite; x = 0 gives NaN.
 // The host build starts from 1.0 / x.
-GM_HD double rcp(double x) {
+template <int N>
+GM_HD void rcp_n(const double (&x)[N], double (&y)[N]) {
+  double r[N], e[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  double r = __builtin_amdgcn_rcp(x);
+    r[i] = __builtin_amdgcn_rcp(x[i]);
 #else
-  double r = 1.0 / x;
+    r[i] = 1.0 / x[i];
 #endif
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  return r;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) e[i] = fma(-x[i], r[i], 1.0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = fma(r[i], e[i], r[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) e[i] = fma(-x[i], r[i], 1.0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) y[i] = fma(r[i], e[i], r[i]);
+}
+
+GM_HD double exp(double x) {
+  const double a[1] = {x};
+  double y[1];
+  exp_n<1>(a, y);
+  return y[0];
+}
+
+GM_HD double cos(double x) {
+  const double a[1] = {x};
+  double y[1];
+  cos_n<1>(a, y);
+  return y[0];
+}
+
+GM_HD double rcp(double x) {
+  const double a[1] = {x};
+  double y[1];
+  rcp_n<1>(a, y);
+  return y[0];
 }
 
 }  // namespace fm

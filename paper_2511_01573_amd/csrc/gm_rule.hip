@@ -97,38 +97,61 @@ struct Fam {
       return true;
     }
   }
+  // (1 + s)^-(d+1) needs (1 + s)^(d+1): binary powering
+  template <int D>
+  __device__ static __forceinline__ double cpk_power(double s) {
+    const double b = 1.0 + s;
+    double y = 1.0, p = b;
+    int e = D + 1;
+    bool first = true;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      if (e & 1) {
+        y = first ? p : y * p;
+        first = false;
+      }
+      e >>= 1;
+      if (e) p = p * p;
+    }
+    return y;
+  }
+  // The outer function G of f = G(s) on N independent arguments at once.
+  template <int D, int N>
+  __device__ static __forceinline__ void outer_n(const DevParams& P, const double (&s)[N],
+                                                 double (&f)[N]) {
+    double a[N];
+    if constexpr (FAM == kOsc) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] = P.c0 + s[i];
+      fm::cos_n<N>(a, f);
+    } else if constexpr (FAM == kProductPeak) {
+      fm::rcp_n<N>(s, f);
+    } else if constexpr (FAM == kCornerPeak) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] = cpk_power<D>(s[i]);
+      fm::rcp_n<N>(a, f);
+    } else if constexpr (FAM == kGaussian || FAM == kC0) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] = -s[i];
+      fm::exp_n<N>(a, f);
+    } else if constexpr (FAM == kDiscontinuous) {
+      fm::exp_n<N>(s, f);
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const double s2 = s[i] * s[i];
+        const double s4 = s2 * s2;
+        const double s8 = s4 * s4;
+        f[i] = (s8 * s2) * s[i];
+      }
+    }
+  }
   template <int D>
   __device__ static __forceinline__ double outer(const DevParams& P, double s) {
-    if constexpr (FAM == kOsc) {
-      return fm::cos(P.c0 + s);
-    } else if constexpr (FAM == kProductPeak) {
-      return fm::rcp(s);
-    } else if constexpr (FAM == kCornerPeak) {
-      // (1 + s)^-(d+1): binary powering, then one reciprocal
-      const double b = 1.0 + s;
-      double y = 1.0, p = b;
-      int e = D + 1;
-      bool first = true;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        if (e & 1) {
-          y = first ? p : y * p;
-          first = false;
-        }
-        e >>= 1;
-        if (e) p = p * p;
-      }
-      return fm::rcp(y);
-    } else if constexpr (FAM == kGaussian || FAM == kC0) {
-      return fm::exp(-s);
-    } else if constexpr (FAM == kDiscontinuous) {
-      return fm::exp(s);
-    } else {
-      const double s2 = s * s;
-      const double s4 = s2 * s2;
-      const double s8 = s4 * s4;
-      return (s8 * s2) * s;
-    }
+    const double a[1] = {s};
+    double f[1];
+    outer_n<D, 1>(P, a, f);
+    return f[0];
   }
 };
 
@@ -159,11 +182,38 @@ __device__ __forceinline__ KSum shfl_xor_ks(KSum v, int m) {
 // ---------------------------------------------------------------------------
 // Corner sweep: binary tree over coordinates D-U .. D-1 below a prefix.
 // ---------------------------------------------------------------------------
+// Arguments of the 2^M corners below prefix s over coordinates J .. J+M-1, in
+// the tree's order (sign + before sign -).
+template <int D, int FAM, int J, int M, bool HAS_PREFIX>
+__device__ __forceinline__ void leaf_args(double s, const double (&t5p)[D], const double (&t5m)[D],
+                                          double* out) {
+  if constexpr (M == 0) {
+    out[0] = s;
+  } else {
+    const double a = HAS_PREFIX ? Fam<FAM>::comb(s, t5p[J]) : t5p[J];
+    const double b = HAS_PREFIX ? Fam<FAM>::comb(s, t5m[J]) : t5m[J];
+    leaf_args<D, FAM, J + 1, M - 1, true>(a, t5p, t5m, out);
+    leaf_args<D, FAM, J + 1, M - 1, true>(b, t5p, t5m, out + (1 << (M - 1)));
+  }
+}
+
+// The last kLeafLog2 levels of the tree are evaluated together: their
+// 2^kLeafLog2 outer functions run interleaved.
+#ifndef GM_LEAF_LOG2
+#define GM_LEAF_LOG2 2
+#endif
+constexpr int kLeafLog2 = GM_LEAF_LOG2;
+
 template <int D, int FAM, int U, int K, bool HAS_PREFIX>
 __device__ __forceinline__ void corner_tree(const DevParams& P, double s, const double (&t5p)[D],
                                             const double (&t5m)[D], double& local) {
-  if constexpr (K == U) {
-    local += Fam<FAM>::template outer<D>(P, s);
+  constexpr int LW = U < kLeafLog2 ? U : kLeafLog2;
+  if constexpr (K == U - LW) {
+    double a[1 << LW], f[1 << LW];
+    leaf_args<D, FAM, D - U + K, LW, HAS_PREFIX>(s, t5p, t5m, a);
+    Fam<FAM>::template outer_n<D, (1 << LW)>(P, a, f);
+#pragma unroll
+    for (int i = 0; i < (1 << LW); ++i) local += f[i];
   } else {
     constexpr int j = D - U + K;
     if constexpr (!HAS_PREFIX && K == 0) {
@@ -339,14 +389,15 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
   for (int i = 0; i < D; ++i) {
     const double v[4] = {F::term(P, i, fma(K.lam2, h[i], c[i])),
                          F::term(P, i, fma(-K.lam2, h[i], c[i])), t3p[i], t3m[i]};
-    double f[4];
+    double a[4], f[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       double s = (i == 0) ? v[q] : F::comb(pc[i], v[q]);
 #pragma unroll GM_UNROLL_A23
       for (int k = i + 1; k < D; ++k) s = F::comb(s, tc[k]);
-      f[q] = F::template outer<D>(P, s);
+      a[q] = s;
     }
+    F::template outer_n<D, 4>(P, a, f);
     ks_add(S2, f[0] + f[1]);
     ks_add(S3, f[2] + f[3]);
     double sc;
@@ -367,14 +418,17 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
       double g = 0.0;
 #pragma unroll GM_UNROLL_A4
       for (int j = i + 1; j < D; ++j) {
+        double a[2], fv[2];
 #pragma unroll
         for (int sj = 0; sj < 2; ++sj) {
           double s = F::comb(m, sj ? t3m[j] : t3p[j]);
 #pragma unroll GM_UNROLL_A4
           for (int k = j + 1; k < D; ++k) s = F::comb(s, tc[k]);
-          const double fv = F::template outer<D>(P, s);
-          g = (j == i + 1 && sj == 0) ? fv : g + fv;
+          a[sj] = s;
         }
+        F::template outer_n<D, 2>(P, a, fv);
+        g = (j == i + 1) ? fv[0] : g + fv[0];
+        g = g + fv[1];
         m = F::comb(m, tc[j]);
       }
       ks_add(S4, g);
@@ -422,8 +476,11 @@ __device__ __forceinline__ RegionResult rule_region_tpr(const DevParams& P, cons
 // lane (a few phase-A values spill to scratch, none inside the corner loop) so
 // a second wavefront hides the latency of the first one's dependent FP64
 // chains and loads.
+#ifndef GM_TPR_WAVES
+#define GM_TPR_WAVES 2
+#endif
 template <int D, int FAM, bool BATCH>
-__global__ __launch_bounds__(kRuleBlock) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(kRuleBlock) __attribute__((amdgpu_waves_per_eu(GM_TPR_WAVES)))
 void rule_tpr_kernel(RuleArgs A) {
   int64_t start, end;
   int buf;
