@@ -368,6 +368,274 @@ int gmo_rule(int fam, int d, const double* params, const double* c, const double
   return r.nonfinite ? GMO_NONFINITE : 0;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Tensor-product Gauss-Kronrod rule (Sec. 3: the framework's second rule,  */
+/* "a tensor-product Gauss-Kronrod rule [Kronrod 1965]").                    */
+/*                                                                          */
+/* Reading: the 1-D pair is the 7-point Gauss-Legendre rule and its 15-point */
+/* Kronrod extension on [-1, 1]; the d-dimensional rule is their tensor      */
+/* product (15^d nodes), the embedded estimate is the tensor Gauss rule      */
+/* (7^d of the same nodes), err = vol |Q_K - Q_G|, and the split axis is the */
+/* axis i whose one-axis estimate e_i = vol |Q_K - Q_{K, G on axis i}| is     */
+/* largest (same tie band as the Genz-Malik rule, relative to the K-sum of   */
+/* |f|).  Usable for 2 <= d <= 6 (its cost grows as 15^d).                  */
+/*                                                                          */
+/* Constants from their definitions, in __float128 (rounded once to double): */
+/*   Gauss nodes: roots of P7 (Newton on the three-term recurrence);         */
+/*   Kronrod extra nodes: roots of the Stieltjes polynomial E8, the monic    */
+/*   even polynomial of degree 8 orthogonal to x^k P7 for k < 8 (coefficients */
+/*   from exact moments); weights: exactness on x^0, x^2, ... (8 symmetric   */
+/*   Kronrod unknowns, 4 Gauss unknowns).  Weights are for the mean measure. */
+/* ------------------------------------------------------------------------ */
+typedef __float128 qf;
+
+static qf q_abs(qf x) { return x < 0 ? -x : x; }
+
+/* P_n(x) and P_n'(x) by the recurrence (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}. */
+static qf q_legendre(int n, qf x, qf* dp) {
+  qf p0 = 1, p1 = x, p2;
+  int k;
+  if (n == 0) {
+    *dp = 0;
+    return 1;
+  }
+  for (k = 1; k < n; ++k) {
+    p2 = ((qf)(2 * k + 1) * x * p1 - (qf)k * p0) / (qf)(k + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  *dp = (qf)n * (x * p1 - p0) / (x * x - 1);
+  return p1;
+}
+
+/* Solve A x = b (n <= 8) by Gaussian elimination with partial pivoting. */
+static void q_solve(int n, qf A[8][8], qf* b) {
+  int i, j, k;
+  for (k = 0; k < n; ++k) {
+    int piv = k;
+    for (i = k + 1; i < n; ++i)
+      if (q_abs(A[i][k]) > q_abs(A[piv][k])) piv = i;
+    if (piv != k) {
+      qf t;
+      for (j = 0; j < n; ++j) {
+        t = A[k][j];
+        A[k][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+      t = b[k];
+      b[k] = b[piv];
+      b[piv] = t;
+    }
+    for (i = k + 1; i < n; ++i) {
+      qf m = A[i][k] / A[k][k];
+      for (j = k; j < n; ++j) A[i][j] -= m * A[k][j];
+      b[i] -= m * b[k];
+    }
+  }
+  for (i = n - 1; i >= 0; --i) {
+    qf s = b[i];
+    for (j = i + 1; j < n; ++j) s -= A[i][j] * b[j];
+    b[i] = s / A[i][i];
+  }
+}
+
+/* int_{-1}^{1} x^a dx */
+static qf q_moment(int a) { return (a % 2) ? (qf)0 : (qf)2 / (qf)(a + 1); }
+
+static int gk_ready = 0;
+static double GK_X[15], GK_WK[15], GK_WG[15];
+
+static void gk_build(void) {
+  qf g[3], kx[4], P7[8], e[5];
+  qf pa[9], pb[9], pc[9];
+  int i, j, m, k;
+  if (gk_ready) return;
+  /* positive Gauss nodes, ascending */
+  for (i = 0; i < 3; ++i) {
+    /* i-th largest root estimate cos(pi (i + 0.75) / 7.5), refined by Newton */
+    qf x = (qf)cos(3.14159265358979323846 * (2 - i + 0.75) / 7.5), dp;
+    for (k = 0; k < 100; ++k) {
+      qf p = q_legendre(7, x, &dp);
+      qf dx = p / dp;
+      x -= dx;
+      if (q_abs(dx) < (qf)1e-33) break;
+    }
+    g[i] = x;
+  }
+  /* coefficients of P7 by the recurrence on coefficient arrays */
+  for (j = 0; j < 9; ++j) pa[j] = pb[j] = 0;
+  pa[0] = 1;       /* P0 */
+  pb[1] = 1;       /* P1 */
+  for (k = 1; k < 7; ++k) {
+    for (j = 0; j < 9; ++j) pc[j] = -(qf)k * pa[j];
+    for (j = 0; j < 8; ++j) pc[j + 1] += (qf)(2 * k + 1) * pb[j];
+    for (j = 0; j < 9; ++j) {
+      pc[j] /= (qf)(k + 1);
+      pa[j] = pb[j];
+      pb[j] = pc[j];
+    }
+  }
+  for (j = 0; j < 8; ++j) P7[j] = pb[j];
+  /* E8(y) = sum_m e_m x^(2m), e_4 = 1: int E8 P7 x^k = 0 for k = 1, 3, 5, 7 */
+  {
+    qf A[8][8], b[8];
+    for (i = 0; i < 4; ++i) {
+      int kk = 2 * i + 1;
+      for (m = 0; m <= 4; ++m) {
+        qf s = 0;
+        for (j = 0; j < 8; ++j)
+          if (P7[j] != 0) s += P7[j] * q_moment(2 * m + j + kk);
+        if (m < 4) A[i][m] = s;
+        else b[i] = -s;
+      }
+    }
+    q_solve(4, A, b);
+    for (m = 0; m < 4; ++m) e[m] = b[m];
+    e[4] = 1;
+  }
+  /* roots of E8 in y = x^2 by bisection, one in each gap (0, g1^2), (g1^2, g2^2), ... , (g3^2, 1) */
+  for (i = 0; i < 4; ++i) {
+    qf lo = i == 0 ? (qf)0 : g[i - 1] * g[i - 1];
+    qf hi = i == 3 ? (qf)1 : g[i] * g[i];
+    qf flo = e[0] + lo * (e[1] + lo * (e[2] + lo * (e[3] + lo)));
+    for (k = 0; k < 240; ++k) {
+      qf mid = (lo + hi) / 2;
+      qf fm = e[0] + mid * (e[1] + mid * (e[2] + mid * (e[3] + mid)));
+      if ((fm < 0) == (flo < 0)) {
+        lo = mid;
+        flo = fm;
+      } else {
+        hi = mid;
+      }
+    }
+    {
+      /* sqrt of the root by Newton from the double estimate */
+      qf y = (lo + hi) / 2, x = (qf)sqrt((double)y);
+      for (k = 0; k < 8; ++k) x = (x + y / x) / 2;
+      kx[i] = x;
+    }
+  }
+  {
+    /* ascending positive nodes: k1 < g1 < k2 < g2 < k3 < g3 < k4 */
+    qf pos[7] = {kx[0], g[0], kx[1], g[1], kx[2], g[2], kx[3]};
+    qf A[8][8], b[8], wk[8], wg[4];
+    /* Kronrod weights: unknowns W0 (centre), W1..W7 (pos[0..6]) */
+    for (m = 0; m < 8; ++m) {
+      A[m][0] = (m == 0) ? (qf)1 : (qf)0;
+      for (j = 0; j < 7; ++j) {
+        qf xp = 1;
+        for (k = 0; k < 2 * m; ++k) xp *= pos[j];
+        A[m][j + 1] = 2 * xp;
+      }
+      b[m] = q_moment(2 * m);
+    }
+    q_solve(8, A, b);
+    for (j = 0; j < 8; ++j) wk[j] = b[j];
+    /* Gauss weights: unknowns V0, V1..V3 on g[0..2] */
+    for (m = 0; m < 4; ++m) {
+      A[m][0] = (m == 0) ? (qf)1 : (qf)0;
+      for (j = 0; j < 3; ++j) {
+        qf xp = 1;
+        for (k = 0; k < 2 * m; ++k) xp *= g[j];
+        A[m][j + 1] = 2 * xp;
+      }
+      b[m] = q_moment(2 * m);
+    }
+    q_solve(4, A, b);
+    for (j = 0; j < 4; ++j) wg[j] = b[j];
+    /* 15 nodes ascending; index 7 is the centre; Gauss nodes at odd indices */
+    GK_X[7] = 0.0;
+    GK_WK[7] = (double)(wk[0] / 2);
+    GK_WG[7] = (double)(wg[0] / 2);
+    for (j = 0; j < 7; ++j) {
+      GK_X[8 + j] = (double)pos[j];
+      GK_X[6 - j] = -(double)pos[j];
+      GK_WK[8 + j] = GK_WK[6 - j] = (double)(wk[j + 1] / 2);
+      GK_WG[8 + j] = GK_WG[6 - j] = (j % 2 == 1) ? (double)(wg[(j + 1) / 2] / 2) : 0.0;
+    }
+  }
+  gk_ready = 1;
+}
+
+void gmo_gk_constants(double x[15], double wk[15], double wg[15]) {
+  gk_build();
+  memcpy(x, GK_X, sizeof GK_X);
+  memcpy(wk, GK_WK, sizeof GK_WK);
+  memcpy(wg, GK_WG, sizeof GK_WG);
+}
+
+int64_t gmo_gk_num_nodes(int d) {
+  int64_t n = 1;
+  int j;
+  for (j = 0; j < d; ++j) n *= 15;
+  return n;
+}
+
+int gmo_rule_gk(int fam, int d, const double* params, const double* c, const double* h, int lvl,
+                double vol_omega, double* out) {
+  ksum SK = {0, 0}, SG = {0, 0}, SM[6];
+  double absK = 0, absE = 0, vol, x[6], e[6], emax = -1.0, band;
+  int k[6], j, i, nonfinite = 0, axis;
+  int64_t t, N;
+  if (d < 2 || d > 6) return GMO_EINVAL;
+  gk_build();
+  memset(SM, 0, sizeof SM);
+  N = gmo_gk_num_nodes(d);
+  for (t = 0; t < N; ++t) {
+    int64_t q = t;
+    double f, WK, WG;
+    /* node index tuple, axis d-1 fastest */
+    for (j = d - 1; j >= 0; --j) {
+      k[j] = (int)(q % 15);
+      q /= 15;
+    }
+    for (j = 0; j < d; ++j) x[j] = fma(GK_X[k[j]], h[j], c[j]);
+    f = gmo_f(fam, d, params, x);
+    if (!isfinite(f)) nonfinite = 1;
+    WK = GK_WK[k[0]];
+    WG = GK_WG[k[0]];
+    for (j = 1; j < d; ++j) {
+      WK = WK * GK_WK[k[j]];
+      WG = WG * GK_WG[k[j]];
+    }
+    ks_add(&SK, WK * f);
+    ks_add(&SG, WG * f);
+    for (i = 0; i < d; ++i) {
+      double WM = (i == 0) ? GK_WG[k[0]] : GK_WK[k[0]];
+      for (j = 1; j < d; ++j) WM = WM * ((j == i) ? GK_WG[k[j]] : GK_WK[k[j]]);
+      ks_add(&SM[i], WM * f);
+    }
+    absK += WK * fabs(f);
+    absE += fabs(WK - WG) * fabs(f);
+  }
+  vol = ldexp(vol_omega, -lvl);
+  out[0] = vol * ks_val(&SK);
+  out[1] = vol * fabs(ks_val(&SK) - ks_val(&SG));
+  out[4] = vol * absK;
+  out[5] = vol * absE;
+  for (i = 0; i < 10; ++i) out[6 + i] = 0.0;
+  out[6] = ks_val(&SK);
+  out[7] = ks_val(&SG);
+  for (i = 0; i < d; ++i) {
+    e[i] = vol * fabs(ks_val(&SK) - ks_val(&SM[i]));
+    out[16 + i] = e[i];
+    if (e[i] > emax) emax = e[i];
+  }
+  band = AXIS_BAND * out[4];
+  axis = -1;
+  for (i = 0; i < d; ++i)
+    if (e[i] >= emax - band && (axis < 0 || h[i] > h[axis])) axis = i;
+  out[2] = (double)axis;
+  {
+    double hp = h[axis] * 0.5;
+    int geo = (c[axis] - hp == c[axis]) || (c[axis] + hp == c[axis]) || (hp == 0.0);
+    out[3] = geo ? 1.0 : 0.0;
+  }
+  if (!(isfinite(out[0]) && isfinite(out[1]))) nonfinite = 1;
+  return nonfinite ? GMO_NONFINITE : 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Adaptive loop (Sec. 3 workflow, Sec. 4 stopping rule).                   */
 /*                                                                          */
@@ -390,6 +658,7 @@ int gmo_rule(int fam, int d, const double* params, const double* c, const double
 /* ------------------------------------------------------------------------ */
 struct gmo_run {
   int fam, d, max_iters, keep_leaves;
+  int rule; /* 0 Genz-Malik, 1 tensor-product Gauss-Kronrod */
   double params[32];
   double rel_tol, abs_tol, vol_omega;
   int64_t max_regions;
@@ -534,12 +803,14 @@ static int phase_eval(gmo_run* r) {
   r->iter++;
   r->stats[GMO_ST_ITERS] = r->iter;
   r->stats[GMO_ST_REGIONS] += r->n;
-  r->stats[GMO_ST_EVALS] += r->n * gmo_num_nodes(d);
+  r->stats[GMO_ST_EVALS] += r->n * (r->rule ? gmo_gk_num_nodes(d) : gmo_num_nodes(d));
   r->stats[GMO_ST_ACTIVE] = r->n;
   if (r->n > r->stats[GMO_ST_MAX_ACTIVE]) r->stats[GMO_ST_MAX_ACTIVE] = r->n;
   for (i = 0; i < r->n; ++i) {
-    int rc = gmo_rule(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
-                      out);
+    int rc = r->rule ? gmo_rule_gk(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i],
+                                   r->vol_omega, out)
+                     : gmo_rule(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i],
+                                r->vol_omega, out);
     if (rc == GMO_NONFINITE) {
       r->I = NAN;
       r->E = NAN;
@@ -654,6 +925,12 @@ static int phase_split(gmo_run* r) {
   free(nl_);
   r->n = n2;
   return GMO_RUNNING;
+}
+
+int gmo_set_rule(gmo_run* r, int rule) {
+  if (rule < 0 || rule > 1 || (rule == 1 && r->d > 6) || r->iter > 0) return GMO_EINVAL;
+  r->rule = rule;
+  return GMO_OK;
 }
 
 int gmo_step(gmo_run* r) {

@@ -17,7 +17,9 @@
  *   - the test integrands of Sec. 4 and their seeded Genz-family
  *     generalisations;
  *   - the derivative of the fixed-tree quadrature with respect to the
- *     integrand parameters, and a lock-step batch of independent integrals.
+ *     integrand parameters, and a lock-step batch of independent integrals;
+ *   - the tensor-product Gauss-Kronrod rule the framework offers besides
+ *     the Genz-Malik rule (Sec. 3), for d <= 6.
  *
  * All floating point is IEEE binary64, built with -ffp-contract=off; every
  * fused multiply-add is written out as fma().
@@ -71,6 +73,15 @@ int64_t gmo_num_nodes(int d);
 void gmo_constants(int d, double lam[5], double w[5], double v[5], double e[5]);
 /* All N(d) nodes of the region (c, h) in visit order: x[N*d], cls[N] in 1..5. */
 void gmo_nodes(int d, const double* c, const double* h, double* x, int* cls);
+/* Tensor-product Gauss-Kronrod rule: the 15 Kronrod abscissae on [-1, 1]
+   (ascending; the 7 Gauss abscissae are those at odd indices), the Kronrod
+   weights and the Gauss weights (0 off the Gauss abscissae), mean measure. */
+void gmo_gk_constants(double x[15], double wk[15], double wg[15]);
+int64_t gmo_gk_num_nodes(int d);
+/* One region with the Gauss-Kronrod rule; out layout as gmo_rule with
+   S[0] = K-sum, S[1] = G-sum and D[i] = the one-axis estimates e_i. */
+int gmo_rule_gk(int fam, int d, const double* params, const double* c, const double* h, int lvl,
+                double vol_omega, double* out);
 /* Integrand value at x; params = a[0..d), u[0..d). */
 double gmo_f(int fam, int d, const double* params, const double* x);
 /* Gradient of f at x with respect to params (out[2d]); returns f. */
@@ -94,6 +105,9 @@ gmo_run* gmo_create(int fam, int d, const double* params, const double* lo, cons
                     double rel_tol, double abs_tol, int64_t max_regions, int init_log2,
                     int max_iters, int keep_leaves, int* status);
 /* One full iteration; returns GMO_RUNNING or the final status. */
+/* Select the rule of a run before its first step: 0 Genz-Malik (default),
+   1 tensor-product Gauss-Kronrod (2 <= d <= 6).  GMO_EINVAL otherwise. */
+int gmo_set_rule(gmo_run* r, int rule);
 int gmo_step(gmo_run* r);
 int gmo_run_to_end(gmo_run* r);
 void gmo_result(const gmo_run* r, double* I, double* E, int* status, int64_t* stats);

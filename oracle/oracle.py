@@ -92,6 +92,13 @@ def lib():
         L.gmo_grad_leaves.restype = C.c_int
         L.gmo_grad_leaves.argtypes = [C.c_int, C.c_int, dp, C.c_int64, dp, dp, i32p, C.c_double,
                                       dp]
+        L.gmo_gk_constants.argtypes = [dp, dp, dp]
+        L.gmo_gk_num_nodes.restype = C.c_int64
+        L.gmo_gk_num_nodes.argtypes = [C.c_int]
+        L.gmo_rule_gk.restype = C.c_int
+        L.gmo_rule_gk.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int, C.c_double, dp]
+        L.gmo_set_rule.restype = C.c_int
+        L.gmo_set_rule.argtypes = [C.c_void_p, C.c_int]
         L.gmo_integrate_batch.restype = C.c_int
         L.gmo_integrate_batch.argtypes = [C.c_int, ip, dp, ip, dp, dp, dp, dp, C.c_int64, C.c_int,
                                           C.c_int, dp, dp, ip, i64p]
@@ -151,8 +158,27 @@ def df(fam: int, params, x):
     return float(val), out
 
 
-def rule(fam: int, params, c, h, lvl: int = 0, vol_omega: float | None = None):
-    """One region (c, h, lvl); returns a dict with Q, err, axis, geo, scales, S, Sabs, D."""
+GENZ_MALIK, GAUSS_KRONROD = 0, 1
+
+
+def gk_constants():
+    """(x[15], wk[15], wg[15]) of the tensor-product Gauss-Kronrod rule."""
+    x, wk, wg = np.zeros(15), np.zeros(15), np.zeros(15)
+    lib().gmo_gk_constants(_d(x)[1], _d(wk)[1], _d(wg)[1])
+    return x, wk, wg
+
+
+def gk_num_nodes(d: int) -> int:
+    return int(lib().gmo_gk_num_nodes(d))
+
+
+def _rule_fn(rule_id: int):
+    return lib().gmo_rule_gk if rule_id == GAUSS_KRONROD else lib().gmo_rule
+
+
+def rule(fam: int, params, c, h, lvl: int = 0, vol_omega: float | None = None, rule_id: int = 0):
+    """One region (c, h, lvl); returns a dict with Q, err, axis, geo, scales, S, Sabs, D
+    (Gauss-Kronrod rule: S[0], S[1] = K and G sums, D = one-axis estimates)."""
     c, cp = _d(c)
     h, hp = _d(h)
     d = c.size
@@ -161,7 +187,7 @@ def rule(fam: int, params, c, h, lvl: int = 0, vol_omega: float | None = None):
         # region volume = prod 2h when lvl == 0
         vol_omega = float(np.prod(2.0 * h))
     out = np.zeros(16 + 32)
-    rc = lib().gmo_rule(fam, d, pp, cp, hp, int(lvl), float(vol_omega), _d(out)[1])
+    rc = _rule_fn(rule_id)(fam, d, pp, cp, hp, int(lvl), float(vol_omega), _d(out)[1])
     return {
         "status": rc, "Q": out[0], "err": out[1], "axis": int(out[2]), "geo": int(out[3]),
         "scaleQ": out[4], "scaleE": out[5], "S": out[6:11].copy(), "Sabs": out[11:16].copy(),
@@ -169,7 +195,7 @@ def rule(fam: int, params, c, h, lvl: int = 0, vol_omega: float | None = None):
     }
 
 
-def rule_many(fam: int, params, c, h, lvl, vol_omega: float):
+def rule_many(fam: int, params, c, h, lvl, vol_omega: float, rule_id: int = 0):
     """Rule on a list of regions; c, h: [n, d]; returns dict of arrays."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     h = np.ascontiguousarray(h, dtype=np.float64)
@@ -181,11 +207,11 @@ def rule_many(fam: int, params, c, h, lvl, vol_omega: float):
     res["axis"] = np.zeros(n, dtype=np.int32)
     res["geo"] = np.zeros(n, dtype=np.int32)
     res["status"] = np.zeros(n, dtype=np.int32)
-    L = lib()
+    fn = _rule_fn(rule_id)
     for i in range(n):
         ci = c[i]
         hi = h[i]
-        rc = L.gmo_rule(fam, d, pp, ci.ctypes.data_as(C.POINTER(C.c_double)),
+        rc = fn(fam, d, pp, ci.ctypes.data_as(C.POINTER(C.c_double)),
                         hi.ctypes.data_as(C.POINTER(C.c_double)), int(lvl[i]), float(vol_omega), op)
         res["status"][i] = rc
         res["Q"][i] = out[0]
@@ -201,7 +227,7 @@ class Run:
     """Handle on one adaptive run of the oracle (Sec. 3 loop)."""
 
     def __init__(self, fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20,
-                 init_log2=12, max_iters=10000, keep_leaves=False):
+                 init_log2=12, max_iters=10000, keep_leaves=False, rule_id=0):
         self.fam = fam
         self.params, pp = _d(params)
         self.lo, lp = _d(lo)
@@ -214,6 +240,8 @@ class Run:
         self.create_status = st.value
         if not self.h:
             raise ValueError(f"oracle rejected arguments (status {st.value})")
+        if rule_id and lib().gmo_set_rule(self.h, int(rule_id)) != OK:
+            raise ValueError(f"oracle rejected rule {rule_id} at d = {self.d}")
         self.vol_omega = float(np.prod(self.hi - self.lo)) if self.d else 1.0
         v = 1.0
         for j in range(self.d):
@@ -279,8 +307,9 @@ class Run:
 
 
 def integrate(fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20, init_log2=12,
-              max_iters=10000):
-    r = Run(fam, params, lo, hi, rel_tol, abs_tol, max_regions, init_log2, max_iters)
+              max_iters=10000, rule_id=0):
+    r = Run(fam, params, lo, hi, rel_tol, abs_tol, max_regions, init_log2, max_iters,
+            rule_id=rule_id)
     r.run()
     return r.result()
 
