@@ -52,7 +52,7 @@ FLOPS_PER_EVAL = {1: 42.75, 2: 12.75, 3: 17.75, 4: 32.5, 5: 32.75, 6: 32.5, 7: 8
 # from; the figure is reported only while those sources are unchanged.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rule_kernel_d8_suite_counters.md")
 RULE_SOURCES = [os.path.join(ROOT, "paper_2511_01573_amd", "csrc", f)
-                for f in ("gm_rule.hip", "gm_common.hpp", "gm_math.hpp", "gm_api.hip")]
+                for f in ("gm_rule.hip", "gm_family.hpp", "gm_common.hpp", "gm_math.hpp", "gm_api.hip")]
 
 
 def parse():
@@ -215,6 +215,39 @@ def bench_config3(gm, W, closed_forms, log2cap: int):
     return out
 
 
+def bench_gk(gm, W, closed_forms):
+    """The tensor-product Gauss-Kronrod rule (7-point Gauss / 15-point
+    Kronrod per axis) against the Genz-Malik rule on the same integrals:
+    time to tolerance, evaluations and accuracy against the closed form."""
+    cases = []
+    c1 = W.config1()
+    cases.append(("gaussian_d3_a5", c1["family"], c1["params"], 3, 1e-6))
+    cases.append(("gaussian_d3_a5", c1["family"], c1["params"], 3, 1e-12))
+    for fam, d in ((1, 4), (2, 4), (4, 5), (5, 3)):
+        cases.append((f"{W.NAMES[fam]}_d{d}", fam, W.family_params(fam, d, 500 + fam), d, 1e-8))
+    out = []
+    for name, fam, p, d, tau in cases:
+        lo, hi = W.unit_box(d)
+        ex = float(closed_forms.exact(fam, p[:d], p[d:]))
+        row = {"name": name, "rel_tol": tau}
+        for rule in (0, 1):
+            gm.set_option("rule", rule)
+            try:
+                gm.integrate(fam, p, lo, hi, tau, 1e-16, 1 << 24)  # warm-up
+                t0 = time.perf_counter()
+                I, E, st = gm.integrate(fam, p, lo, hi, tau, 1e-16, 1 << 24)
+                dt = time.perf_counter() - t0
+                s = gm.last_stats()
+            finally:
+                gm.set_option("rule", 0)
+            key = "gk" if rule else "gm"
+            row[key] = {"status": st, "seconds": dt, "evals": s["evals"],
+                        "regions": s["regions_evaluated"], "evals_per_s": s["evals"] / dt,
+                        "rel_err_vs_closed_form": abs(I - ex) / abs(ex)}
+        out.append(row)
+    return out
+
+
 def bench_grad(gm, W, closed_forms, tau: float, cap: int):
     """C5 gradient (d = 8 Gaussian, 16 parameters): one gm_integrate_grad call
     against 1 + 32 gm_integrate calls (the estimate plus central differences
@@ -314,6 +347,7 @@ def main():
         out["batch"] = bench_batch(gm, W, closed_forms)
         out["grad"] = bench_grad(gm, W, closed_forms, args.grad_tau, 1 << args.grad_log2cap)
         out["config3"] = bench_config3(gm, W, closed_forms, args.config3_log2cap)
+        out["gauss_kronrod"] = bench_gk(gm, W, closed_forms)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

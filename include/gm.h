@@ -156,6 +156,13 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  *   "lanes_per_region"   0 = automatic, else 1..64 power of two (rule kernel mapping)
  *   "timing"             1 = record the rule kernel's device time with hipEvents on
  *                        the call's stream, 2 = every phase (default 0 = off)
+ *   "rule"               0 = the Genz-Malik rule (Sec. 2, default); 1 = the
+ *                        tensor-product Gauss-Kronrod rule (Sec. 3: 7-point
+ *                        Gauss / 15-point Kronrod per axis, 15^d nodes,
+ *                        err = vol |Q_K - Q_G|), for gm_integrate and
+ *                        gm_eval_regions with 2 <= d <= 6 (GM_EINVAL above;
+ *                        gm_integrate_batch and gm_integrate_grad return
+ *                        GM_EINVAL while it is selected)
  *   "log"                1 = print one line per iteration to stderr (default 0)
  */
 int gm_set_option(const char* key, int64_t value);

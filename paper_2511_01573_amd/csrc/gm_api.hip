@@ -535,6 +535,7 @@ int validate(int fam, const double* params, int d, const double* lo, const doubl
   if (!(rel_tol >= 0.0) || !(abs_tol >= 0.0) || !std::isfinite(rel_tol) || !std::isfinite(abs_tol))
     return GM_EINVAL;
   if (rel_tol == 0.0 && abs_tol == 0.0) return GM_EINVAL;
+  if (g_opt.rule == 1 && d > kGkMaxDim) return GM_EINVAL;
   for (int j = 0; j < d; ++j)
     if (!std::isfinite(lo[j]) || !std::isfinite(hi[j]) || !(lo[j] < hi[j])) return GM_EINVAL;
   for (int j = 0; j < 2 * d; ++j)
@@ -557,8 +558,33 @@ RuleKernelFn rule_kernel(int d, int fam, int log2l, bool batch) {
   }
 }
 
+RuleKernelFn gk_kernel(int d, int fam) {
+  switch (fam) {
+    case 1: return gk_kernel_f1(d);
+    case 2: return gk_kernel_f2(d);
+    case 3: return gk_kernel_f3(d);
+    case 4: return gk_kernel_f4(d);
+    case 5: return gk_kernel_f5(d);
+    case 6: return gk_kernel_f6(d);
+    case 7: return gk_kernel_f7(d);
+    default: return nullptr;
+  }
+}
+
+// Mapping code of the Gauss-Kronrod kernel (one wavefront per region).
+constexpr int kMapGk = 100;
+
+int64_t nodes_per_region(int d) {
+  if (g_opt.rule == 1) {
+    int64_t n = 1;
+    for (int j = 0; j < d; ++j) n *= 15;
+    return n;
+  }
+  return gm_num_nodes(d);
+}
+
 hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s) {
-  RuleKernelFn fn = rule_kernel(d, fam, log2l, false);
+  RuleKernelFn fn = log2l == kMapGk ? gk_kernel(d, fam) : rule_kernel(d, fam, log2l, false);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kRuleBlockSize), 0, s, a);
   return hipGetLastError();
@@ -576,6 +602,7 @@ bool mapping_allowed(int d, int log2l) {
 constexpr int64_t kTargetLanes = 131072;
 
 int choose_mapping(int d, int64_t n) {
+  if (g_opt.rule == 1) return kMapGk;
   const int forced = g_opt.lanes_per_region;
   if (forced > 0) {
     int l = -1;
@@ -598,7 +625,9 @@ int choose_mapping(int d, int64_t n) {
 }
 
 int rule_grid(int log2l, int64_t n) {
-  const int64_t per_block = (log2l < 0) ? kRuleBlockSize : (kRuleBlockSize >> log2l);
+  const int64_t per_block = log2l == kMapGk ? kRuleBlockSize / 64
+                            : (log2l < 0)   ? kRuleBlockSize
+                                            : (kRuleBlockSize >> log2l);
   const int64_t g = (n + per_block - 1) / per_block;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxRuleGrid));
 }
@@ -789,7 +818,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       const int map = choose_mapping(d, nb);
       const int rg = rule_grid(map, nb);
       const int tg = tile_grid_for(nb);
-      g_stats.lanes_per_region = map < 0 ? 1 : (1 << map);
+      g_stats.lanes_per_region = map == kMapGk ? 64 : map < 0 ? 1 : (1 << map);
       if (timing) GM_HIP(hipEventRecord(ev[k][0], s));
       GM_HIP(launch_rule(d, fam, map, ra, rg, s));
       if (timing) GM_HIP(hipEventRecord(ev[k][1], s));
@@ -850,7 +879,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   out->vol_omega = vol;
   g_stats.iterations = hst.iter;
   g_stats.regions_evaluated = hst.regions_evaluated;
-  g_stats.evals = hst.regions_evaluated * gm_num_nodes(d);
+  g_stats.evals = hst.regions_evaluated * nodes_per_region(d);
   g_stats.max_active = hst.max_active;
   g_stats.final_active = hst.n_active;
   g_stats.finished = hst.finished;
@@ -1037,6 +1066,9 @@ int gm_set_option(const char* key, int64_t value) {
   } else if (k == "timing") {
     if (value < 0 || value > 2) return GM_EINVAL;
     g_opt.timing = (int)value;
+  } else if (k == "rule") {
+    if (value < 0 || value > 1) return GM_EINVAL;
+    g_opt.rule = (int)value;
   } else if (k == "log") {
     g_opt.log = value ? 1 : 0;
   } else {

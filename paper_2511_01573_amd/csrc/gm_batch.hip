@@ -604,6 +604,7 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
               double* out_est, double* out_err, int* out_status, hipStream_t s) {
   const auto t_start = std::chrono::steady_clock::now();
   const Options& opt = options();
+  if (opt.rule != 0) return GM_EINVAL;  // batch items use the Genz-Malik rule
   // Per-item offsets into the packed inputs and validation.
   std::vector<int64_t> poff(n), boff(n);
   int64_t po = 0, bo = 0;

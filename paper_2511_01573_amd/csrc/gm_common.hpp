@@ -2,8 +2,8 @@
 //
 // Method: arXiv 2511.01573 (adaptive Genz-Malik cubature, Sec. 2-4).  This
 // header holds the kernel argument blocks, the device status block that drives
-// the iteration (Sec. 3 loop), compensated (double-double) summation and the
-// integrand definitions (Sec. 4 test functions and their Genz families).
+// the iteration (Sec. 3 loop), the integrand parameter block (Sec. 4 test
+// functions and their Genz families) and compensated (double-double) summation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -126,60 +126,6 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
-// ---------------------------------------------------------------------------
-// Integrands (Sec. 4).  The argument of every family is a left-to-right sum
-// over coordinates j = 0..d-1, exactly as written in the formulas; the
-// transcendental comes from the device math library.
-// ---------------------------------------------------------------------------
-template <int D, int FAM>
-__device__ __forceinline__ double integrand(const DevParams& P, const double (&x)[D]) {
-  if constexpr (FAM == kOsc) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) s = s + P.a[j] * x[j];
-    return cos(P.c0 + s);
-  } else if constexpr (FAM == kProductPeak) {
-    double den = 1.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      double t = x[j] - P.u[j];
-      den = den * (P.inv_a2[j] + t * t);
-    }
-    return 1.0 / den;
-  } else if constexpr (FAM == kCornerPeak) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) s = s + P.a[j] * x[j];
-    return pow(1.0 + s, -(double)(D + 1));
-  } else if constexpr (FAM == kGaussian) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      double t = P.a[j] * (x[j] - P.u[j]);
-      s = s + t * t;
-    }
-    return exp(-s);
-  } else if constexpr (FAM == kC0) {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) s = s + P.a[j] * fabs(x[j] - P.u[j]);
-    return exp(-s);
-  } else if constexpr (FAM == kDiscontinuous) {
-    bool out = false;
-#pragma unroll
-    for (int j = 0; j < D; ++j) out = out || (x[j] > P.u[j]);
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) s = s + P.a[j] * x[j];
-    return out ? 0.0 : exp(s);
-  } else {
-    double s = 0.0;
-#pragma unroll
-    for (int j = 0; j < D; ++j) s = s + x[j] * x[j];
-    return pow(s, 11.0);
-  }
-}
-
 // Kernel arguments of the rule kernel (Sec. 2 evaluation of every region).
 struct RuleArgs {
   DevParams P;
@@ -224,5 +170,16 @@ RuleKernelFn rule_kernel_f6(int d, int log2l, bool batch);
 RuleKernelFn rule_kernel_f7(int d, int log2l, bool batch);
 constexpr int kTprMaxDim = 10;
 constexpr int kRuleBlockSize = 256;
+
+// Tensor-product Gauss-Kronrod rule kernels (one wavefront per region), one
+// launcher per family, 2 <= d <= kGkMaxDim.
+RuleKernelFn gk_kernel_f1(int d);
+RuleKernelFn gk_kernel_f2(int d);
+RuleKernelFn gk_kernel_f3(int d);
+RuleKernelFn gk_kernel_f4(int d);
+RuleKernelFn gk_kernel_f5(int d);
+RuleKernelFn gk_kernel_f6(int d);
+RuleKernelFn gk_kernel_f7(int d);
+constexpr int kGkMaxDim = 6;
 
 }  // namespace gm

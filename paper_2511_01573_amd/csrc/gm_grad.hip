@@ -53,6 +53,7 @@ extern "C" int gm_integrate_grad(int integrand_id, const double* params, int d, 
   int rc = validate(integrand_id, params, d, lo, hi, rel_tol, abs_tol);
   if (rc != GM_OK) return rc;
   if (!out_est || !out_err || !out_grad) return GM_EINVAL;
+  if (options().rule != 0) return GM_EINVAL;  // the adjoint is written for the Genz-Malik rule
   std::lock_guard<std::mutex> lk(api_mutex());
   hipStream_t s = (hipStream_t)stream;
   RunResult rr;

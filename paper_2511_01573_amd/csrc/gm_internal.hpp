@@ -20,6 +20,7 @@ struct Options {
   int lanes_per_region = 0;  // rule-kernel mapping (0 = automatic)
   int timing = 0;            // per-phase hipEvent timing
   int log = 0;               // per-iteration log to stderr
+  int rule = 0;              // 0 Genz-Malik, 1 tensor-product Gauss-Kronrod (d <= 6)
 };
 
 // Byte offsets of the device buffers of one run inside the workspace.
