@@ -652,13 +652,18 @@ int gmo_rule_gk(int fam, int d, const double* params, const double* c, const dou
 /*      (b) fl(|I| + err) == |I|    (round-off guard), or                   */
 /*      (c) halving along its axis changes nothing (geometry guard).         */
 /* 6. Retired regions join I_fin, E_fin (and the leaf list).                 */
-/* 7. No region left -> precision limit; 2*n_keep > capacity -> stop.        */
+/* 7. No region left -> precision limit; 2*n_keep > capacity -> stop, or,   */
+/*    with memory-pressure pruning on, relax the budget of step 5(a) by the  */
+/*    smallest power of two 2^k (k = 1..64) that leaves at most capacity/2   */
+/*    regions unretired, retire the rest and go on (a run that pruned and    */
+/*    then runs out of regions ends with the capacity status).               */
 /* 8. Split each kept region in half along its axis: child "-" at rank p,   */
 /*    child "+" at n_keep + p (stable order).                               */
 /* ------------------------------------------------------------------------ */
 struct gmo_run {
   int fam, d, max_iters, keep_leaves;
   int rule; /* 0 Genz-Malik, 1 tensor-product Gauss-Kronrod */
+  int prune, pruned; /* memory-pressure pruning: enabled, happened */
   double params[32];
   double rel_tol, abs_tol, vol_omega;
   int64_t max_regions;
@@ -859,10 +864,45 @@ static int phase_eval(gmo_run* r) {
     trace_push(r, r->n, nfin);
   }
   if (r->n_keep == 0) {
-    r->status = GMO_PRECISION_LIMIT;
+    r->status = r->pruned ? GMO_MAX_REGIONS : GMO_PRECISION_LIMIT;
     return r->status;
   }
   return GMO_RUNNING;
+}
+
+/* Smallest k in 1..64 with err <= T 2^(k - lvl) (65: none). */
+static int prune_level(double err, double T, int lvl) {
+  int k;
+  for (k = 1; k <= 64; ++k)
+    if (err <= ldexp(T, k - lvl)) return k;
+  return 65;
+}
+
+/* Memory-pressure pruning (step 7): returns 1 when the kept set was cut down
+   to at most capacity/2 regions, 0 when no budget factor up to 2^64 does it. */
+static int prune(gmo_run* r) {
+  int64_t hist[66], i, above = r->n_keep, half = r->max_regions / 2, nfin;
+  int k, ks = -1;
+  for (k = 0; k < 66; ++k) hist[k] = 0;
+  for (i = 0; i < r->n; ++i)
+    if (!r->fin[i]) hist[prune_level(r->err[i], r->T, r->lvl[i])]++;
+  for (k = 1; k <= 64; ++k) {
+    above -= hist[k];
+    if (above <= half) {
+      ks = k;
+      break;
+    }
+  }
+  if (ks < 0) return 0;
+  for (i = 0; i < r->n; ++i)
+    if (!r->fin[i] && r->err[i] <= ldexp(r->T, ks - r->lvl[i])) {
+      r->fin[i] = 1;
+      r->n_keep--;
+    }
+  r->pruned = 1;
+  nfin = r->n - r->n_keep;
+  r->trc[2 * (r->ntr - 1) + 1] = nfin; /* this iteration's trace entry */
+  return 1;
 }
 
 /* Phase C: commit retired regions and split the kept ones. */
@@ -933,14 +973,24 @@ int gmo_set_rule(gmo_run* r, int rule) {
   return GMO_OK;
 }
 
+int gmo_set_prune(gmo_run* r, int on) {
+  if (on < 0 || on > 1 || r->iter > 0) return GMO_EINVAL;
+  r->prune = on;
+  return GMO_OK;
+}
+
+int gmo_pruned(const gmo_run* r) { return r->pruned; }
+
 int gmo_step(gmo_run* r) {
   int st;
   if (r->status != GMO_RUNNING) return r->status;
   st = phase_eval(r);
   if (st != GMO_RUNNING) return st;
   if (2 * r->n_keep > r->max_regions) {
-    r->status = GMO_MAX_REGIONS;
-    return r->status;
+    if (!r->prune || !prune(r) || r->n_keep == 0) {
+      r->status = GMO_MAX_REGIONS;
+      return r->status;
+    }
   }
   st = phase_split(r);
   if (st != GMO_RUNNING) r->status = st;

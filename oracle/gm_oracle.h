@@ -108,6 +108,11 @@ gmo_run* gmo_create(int fam, int d, const double* params, const double* lo, cons
 /* Select the rule of a run before its first step: 0 Genz-Malik (default),
    1 tensor-product Gauss-Kronrod (2 <= d <= 6).  GMO_EINVAL otherwise. */
 int gmo_set_rule(gmo_run* r, int rule);
+/* Memory-pressure pruning (before the first step): when the kept regions would
+   overflow the capacity, relax the classifier's budget by the smallest power
+   of two that makes them fit and continue.  gmo_pruned: whether it happened. */
+int gmo_set_prune(gmo_run* r, int on);
+int gmo_pruned(const gmo_run* r);
 int gmo_step(gmo_run* r);
 int gmo_run_to_end(gmo_run* r);
 void gmo_result(const gmo_run* r, double* I, double* E, int* status, int64_t* stats);

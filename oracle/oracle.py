@@ -99,6 +99,10 @@ def lib():
         L.gmo_rule_gk.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int, C.c_double, dp]
         L.gmo_set_rule.restype = C.c_int
         L.gmo_set_rule.argtypes = [C.c_void_p, C.c_int]
+        L.gmo_set_prune.restype = C.c_int
+        L.gmo_set_prune.argtypes = [C.c_void_p, C.c_int]
+        L.gmo_pruned.restype = C.c_int
+        L.gmo_pruned.argtypes = [C.c_void_p]
         L.gmo_integrate_batch.restype = C.c_int
         L.gmo_integrate_batch.argtypes = [C.c_int, ip, dp, ip, dp, dp, dp, dp, C.c_int64, C.c_int,
                                           C.c_int, dp, dp, ip, i64p]
@@ -227,7 +231,7 @@ class Run:
     """Handle on one adaptive run of the oracle (Sec. 3 loop)."""
 
     def __init__(self, fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20,
-                 init_log2=12, max_iters=10000, keep_leaves=False, rule_id=0):
+                 init_log2=12, max_iters=10000, keep_leaves=False, rule_id=0, prune=False):
         self.fam = fam
         self.params, pp = _d(params)
         self.lo, lp = _d(lo)
@@ -242,6 +246,8 @@ class Run:
             raise ValueError(f"oracle rejected arguments (status {st.value})")
         if rule_id and lib().gmo_set_rule(self.h, int(rule_id)) != OK:
             raise ValueError(f"oracle rejected rule {rule_id} at d = {self.d}")
+        if prune:
+            lib().gmo_set_prune(self.h, 1)
         self.vol_omega = float(np.prod(self.hi - self.lo)) if self.d else 1.0
         v = 1.0
         for j in range(self.d):
@@ -262,7 +268,7 @@ class Run:
         lib().gmo_result(self.h, C.byref(I), C.byref(E), C.byref(st),
                          stats.ctypes.data_as(C.POINTER(C.c_int64)))
         out = {"I": I.value, "E": E.value, "status": st.value,
-               "escale": float(lib().gmo_escale(self.h))}
+               "escale": float(lib().gmo_escale(self.h)), "pruned": bool(lib().gmo_pruned(self.h))}
         out.update({k: int(v) for k, v in zip(STAT_NAMES, stats)})
         return out
 
@@ -307,9 +313,9 @@ class Run:
 
 
 def integrate(fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20, init_log2=12,
-              max_iters=10000, rule_id=0):
+              max_iters=10000, rule_id=0, prune=False):
     r = Run(fam, params, lo, hi, rel_tol, abs_tol, max_regions, init_log2, max_iters,
-            rule_id=rule_id)
+            rule_id=rule_id, prune=prune)
     r.run()
     return r.result()
 
