@@ -251,6 +251,34 @@ def bench_gk(gm, W, closed_forms):
     return out
 
 
+def bench_prune(gm, W, closed_forms):
+    """Memory-pressure pruning on the suite cases that outgrow their store:
+    the oscillatory integral at rel_tol 1e-7 with 2^24 regions, and two d = 8
+    cases on a store of 2^18 regions, each without and with pruning."""
+    out = []
+    cases = [c for c in W.config2(taus=(1e-7,)) if c["family"] == 1]
+    cases += [dict(c, max_regions=1 << 18) for c in W.config2(taus=(1e-7,)) if c["family"] in (4, 5)]
+    for c in cases:
+        d = len(c["lo"])
+        ex = float(closed_forms.exact(c["family"], c["params"][:d], c["params"][d:]))
+        row = {"name": c["name"], "max_regions": c["max_regions"]}
+        for prune in (0, 1):
+            gm.set_option("prune", prune)
+            try:
+                t0 = time.perf_counter()
+                I, E, st = gm.integrate(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"],
+                                        c["abs_tol"], c["max_regions"])
+                dt = time.perf_counter() - t0
+                s = gm.last_stats()
+            finally:
+                gm.set_option("prune", 0)
+            row["pruned" if prune else "plain"] = {
+                "status": st, "seconds": dt, "iterations": s["iterations"], "evals": s["evals"],
+                "E_over_I": E / abs(I), "rel_err_vs_closed_form": abs(I - ex) / abs(ex)}
+        out.append(row)
+    return out
+
+
 def bench_grad(gm, W, closed_forms, tau: float, cap: int):
     """C5 gradient (d = 8 Gaussian, 16 parameters): one gm_integrate_grad call
     against 1 + 32 gm_integrate calls (the estimate plus central differences
@@ -351,6 +379,7 @@ def main():
         out["grad"] = bench_grad(gm, W, closed_forms, args.grad_tau, 1 << args.grad_log2cap)
         out["config3"] = bench_config3(gm, W, closed_forms, args.config3_log2cap)
         out["gauss_kronrod"] = bench_gk(gm, W, closed_forms)
+        out["prune"] = bench_prune(gm, W, closed_forms)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

@@ -163,6 +163,14 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  *                        gm_eval_regions with 2 <= d <= 6 (GM_EINVAL above;
  *                        gm_integrate_batch and gm_integrate_grad return
  *                        GM_EINVAL while it is selected)
+ *   "prune"              1 = memory-pressure pruning: when the kept regions would
+ *                        overflow max_regions, relax the classifier's budget
+ *                        (err <= T 2^-lvl) by the smallest power of two 2^k,
+ *                        k = 1..64, that makes them fit and continue instead of
+ *                        stopping; a run that pruned returns GM_OK if E <= T is
+ *                        still reached, else GM_MAX_REGIONS with the refined
+ *                        (I, E).  gm_integrate / gm_integrate_grad only
+ *                        (gm_integrate_batch returns GM_EINVAL).  Default 0.
  *   "log"                1 = print one line per iteration to stderr (default 0)
  */
 int gm_set_option(const char* key, int64_t value);

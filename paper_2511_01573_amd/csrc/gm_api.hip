@@ -38,6 +38,7 @@ namespace gm {
 constexpr int kTile = 1024;        // regions per classify/scatter tile
 constexpr int kTileThreads = 256;  // 4 regions per thread per tile
 constexpr int kMaxRuleGrid = 16384;
+constexpr int kPruneBins = 66;  // budget factors 2^1 .. 2^64, bin 65 = beyond
 constexpr int kMaxTileGrid = 8192;
 
 struct InitArgs {
@@ -67,8 +68,10 @@ __global__ void init_kernel(InitArgs A) {
 }
 
 // Global reduction of the rule kernel's block partials and the stopping rule.
-__global__ __launch_bounds__(1024) void reduce_kernel(Status* st, const double* partials, int np) {
+__global__ __launch_bounds__(1024) void reduce_kernel(Status* st, const double* partials, int np,
+                                                      int64_t* hist) {
   if (st->done) return;
+  for (int b = threadIdx.x; b < kPruneBins; b += 1024) hist[b] = 0;
   dd q = {0.0, 0.0}, e = {0.0, 0.0};
   for (int p = threadIdx.x; p < np; p += 1024) {
     q = dd_sum(q, dd{partials[4 * p + 0], partials[4 * p + 1]});
@@ -124,23 +127,46 @@ struct ClassifyArgs {
   int64_t* TK;    // kept per tile
   double* TQ;     // retired Q per tile (double-double)
   double* TE;     // retired err per tile
+  int64_t* HIST;  // kept regions per smallest sufficient budget factor (pruning)
 };
+
+// Smallest k in 1..64 with err <= T 2^(k - lvl), 65 if none: the budget factor
+// that would retire the region (memory-pressure pruning).
+__device__ __forceinline__ int prune_level(double err, double T, int lvl) {
+  for (int k = 1; k <= 64; ++k)
+    if (err <= ldexp(T, k - lvl)) return k;
+  return 65;
+}
 
 // Classifier (reading of Sec. 3's "discards subregions whose contribution to
 // the error is negligible"): retire when err <= T * 2^-lvl (the region's
 // error density is within the global budget), when |I| + err == |I|
 // (round-off guard), or when halving along the axis changes nothing
 // (geometry guard, flagged by the rule kernel in bit 7 of the axis byte).
+// With memory-pressure pruning on, the first pass also histograms the kept
+// regions by the budget factor that would retire them; when the kept set
+// overflows the store the scan kernel picks the smallest sufficient factor
+// 2^k and the second pass (SECOND) classifies again with err <= T 2^(k - lvl)
+// added to the retire test.
+template <bool SECOND>
 __global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) {
   const Status* st = A.st;
   if (st->done) return;
+  if (SECOND && !st->reclassify) return;
   const int64_t n = st->n_active;
   const double T = st->T;
   const double aI = fabs(st->I);
+  const int prune_k = SECOND ? st->prune_k : 0;
+  const bool hist_on = !SECOND && st->prune_on;
   const uint16_t* __restrict__ L = A.L[st->buf];
   const int64_t nt = (n + kTile - 1) / kTile;
   __shared__ int64_t sk[kTileThreads / 64];
   __shared__ dd sq[kTileThreads / 64], se[kTileThreads / 64];
+  __shared__ unsigned int shist[kPruneBins];
+  if (hist_on) {
+    for (int b = threadIdx.x; b < kPruneBins; b += kTileThreads) shist[b] = 0;
+    __syncthreads();
+  }
   for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     int64_t keep = 0;
     dd q = {0.0, 0.0}, e = {0.0, 0.0};
@@ -149,7 +175,10 @@ __global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) 
       const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
       if (r < n) {
         const double err = A.ERR[r];
-        const bool fin = (err <= ldexp(T, -(int)L[r])) || (aI + err == aI) || (A.AXIS[r] & 0x80);
+        const int lvl = L[r];
+        bool fin = (err <= ldexp(T, -lvl)) || (aI + err == aI) || (A.AXIS[r] & 0x80);
+        if (SECOND && !fin) fin = err <= ldexp(T, prune_k - lvl);
+        if (hist_on && !fin) atomicAdd(&shist[prune_level(err, T, lvl)], 1u);
         A.FLAG[r] = fin ? 1 : 0;
         if (fin) {
           dd_add(q, A.Q[r]);
@@ -185,13 +214,23 @@ __global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) 
     }
     __syncthreads();
   }
+  if (hist_on) {
+    for (int b = threadIdx.x; b < kPruneBins; b += kTileThreads)
+      if (shist[b]) atomicAdd((unsigned long long*)&A.HIST[b], (unsigned long long)shist[b]);
+  }
 }
 
 // Exclusive scan of the per-tile keep counts (one workgroup), capacity and
-// precision checks, and the commit of the retired partial sums.
+// precision checks, and the commit of the retired partial sums.  When the
+// kept set overflows the store and pruning is on, the first pass picks the
+// budget factor and leaves the commit to the second pass (SECOND), which runs
+// after the second classification.
+template <bool SECOND>
 __global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* TK, int64_t* TOFF,
-                                                    const double* TQ, const double* TE) {
+                                                    const double* TQ, const double* TE,
+                                                    const int64_t* HIST) {
   if (st->done) return;
+  if (SECOND && !st->reclassify) return;
   const int64_t n = st->n_active;
   const int64_t nt = (n + kTile - 1) / kTile;
   const int64_t per = (nt + 1023) / 1024;
@@ -238,12 +277,26 @@ __global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* T
     tq = dd_sum(tq, sq[i]);
     te = dd_sum(te, se[i]);
   }
+  if (SECOND) st->reclassify = 0;
   if (total == 0) {
-    st->status = GM_PRECISION_LIMIT;
+    // a run that pruned and then ran out of regions was limited by the store
+    st->status = st->pruned ? GM_MAX_REGIONS : GM_PRECISION_LIMIT;
     st->done = 1;
     return;
   }
   if (2 * total > st->cap) {
+    if (!SECOND && st->prune_on) {
+      int64_t above = total;
+      for (int k = 1; k <= 64; ++k) {
+        above -= HIST[k];
+        if (2 * above <= st->cap) {
+          st->prune_k = k;
+          st->pruned = 1;
+          st->reclassify = 1;
+          return;
+        }
+      }
+    }
     st->status = GM_MAX_REGIONS;
     st->done = 1;
     return;
@@ -465,6 +518,7 @@ Layout make_layout(int d, int64_t cap) {
   L.TE = take(sizeof(double) * 2 * ntiles);
   L.PART = take(sizeof(double) * 4 * kMaxRuleGrid);
   L.ST = take(sizeof(Status));
+  L.HIST = take(sizeof(int64_t) * kPruneBins);
   L.total = off;
   return L;
 }
@@ -754,6 +808,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   ca.TK = (int64_t*)(base + lay.TK);
   ca.TQ = (double*)(base + lay.TQ);
   ca.TE = (double*)(base + lay.TE);
+  ca.HIST = (int64_t*)(base + lay.HIST);
 
   ScatterArgs sa;
   std::memset(&sa, 0, sizeof sa);
@@ -776,6 +831,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   hst.max_iters = g_opt.max_iters;
   hst.rel_tol = rel_tol;
   hst.abs_tol = abs_tol;
+  hst.prune_on = g_opt.prune;
   GM_HIP(hipMemcpyAsync(st, &hst, sizeof hst, hipMemcpyHostToDevice, s));
   {
     int g = (int)std::min<int64_t>((n0 + 255) / 256, 4096);
@@ -822,14 +878,22 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       if (timing) GM_HIP(hipEventRecord(ev[k][0], s));
       GM_HIP(launch_rule(d, fam, map, ra, rg, s));
       if (timing) GM_HIP(hipEventRecord(ev[k][1], s));
-      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, st, ra.partials, rg);
+      hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, st, ra.partials, rg, ca.HIST);
       GM_HIP(hipGetLastError());
       if (phases) GM_HIP(hipEventRecord(ev[k][2], s));
-      hipLaunchKernelGGL(classify_kernel, dim3(tg), dim3(kTileThreads), 0, s, ca);
+      hipLaunchKernelGGL(classify_kernel<false>, dim3(tg), dim3(kTileThreads), 0, s, ca);
       GM_HIP(hipGetLastError());
       if (phases) GM_HIP(hipEventRecord(ev[k][3], s));
-      hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, st, ca.TK, sa.TOFF, ca.TQ, ca.TE);
+      hipLaunchKernelGGL(scan_kernel<false>, dim3(1), dim3(1024), 0, s, st, ca.TK, sa.TOFF, ca.TQ,
+                         ca.TE, ca.HIST);
       GM_HIP(hipGetLastError());
+      if (g_opt.prune) {
+        hipLaunchKernelGGL(classify_kernel<true>, dim3(tg), dim3(kTileThreads), 0, s, ca);
+        GM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(scan_kernel<true>, dim3(1), dim3(1024), 0, s, st, ca.TK, sa.TOFF, ca.TQ,
+                           ca.TE, ca.HIST);
+        GM_HIP(hipGetLastError());
+      }
       hipLaunchKernelGGL(scatter_fn(d), dim3(tg), dim3(kTileThreads), 0, s, sa);
       GM_HIP(hipGetLastError());
       if (phases) GM_HIP(hipEventRecord(ev[k][4], s));
@@ -1069,6 +1133,9 @@ int gm_set_option(const char* key, int64_t value) {
   } else if (k == "rule") {
     if (value < 0 || value > 1) return GM_EINVAL;
     g_opt.rule = (int)value;
+  } else if (k == "prune") {
+    if (value < 0 || value > 1) return GM_EINVAL;
+    g_opt.prune = (int)value;
   } else if (k == "log") {
     g_opt.log = value ? 1 : 0;
   } else {

@@ -605,6 +605,7 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
   const auto t_start = std::chrono::steady_clock::now();
   const Options& opt = options();
   if (opt.rule != 0) return GM_EINVAL;  // batch items use the Genz-Malik rule
+  if (opt.prune != 0) return GM_EINVAL;  // the batch's shared capacity has its own rule
   // Per-item offsets into the packed inputs and validation.
   std::vector<int64_t> poff(n), boff(n);
   int64_t po = 0, bo = 0;

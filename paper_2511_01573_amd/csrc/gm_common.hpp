@@ -69,7 +69,11 @@ struct Status {
   double I, E, T;
   double ifin_hi, ifin_lo, efin_hi, efin_lo;
   double rel_tol, abs_tol;
-  int64_t pad[4];
+  int32_t prune_on;     // memory-pressure pruning enabled
+  int32_t pruned;       // pruning happened in this run
+  int32_t reclassify;   // this iteration is classified again with the relaxed budget
+  int32_t prune_k;      // budget factor 2^prune_k of that second pass
+  int64_t pad[2];
 };
 
 // ---------------------------------------------------------------------------

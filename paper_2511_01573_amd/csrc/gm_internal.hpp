@@ -21,6 +21,7 @@ struct Options {
   int timing = 0;            // per-phase hipEvent timing
   int log = 0;               // per-iteration log to stderr
   int rule = 0;              // 0 Genz-Malik, 1 tensor-product Gauss-Kronrod (d <= 6)
+  int prune = 0;             // memory-pressure pruning instead of stopping at capacity
 };
 
 // Byte offsets of the device buffers of one run inside the workspace.
@@ -28,7 +29,7 @@ struct Layout {
   size_t C[2], H[2], L[2];
   size_t Q, ERR, AXIS, FLAG;
   size_t TK, TOFF, TQ, TE;
-  size_t PART, ST;
+  size_t PART, ST, HIST;
   size_t total;
 };
 
