@@ -52,7 +52,7 @@ def time_batch(args, cap, reps=2):
     return best
 
 
-def tune(batch=None, per_group=128, cap=1 << 24, verbose=True):
+def tune(batch=None, per_group=128, cap=1 << 27, verbose=True):
     batch = batch or W.config4()
     table = {}
     for (d, fam), idx in sorted(group_batches(batch).items()):
