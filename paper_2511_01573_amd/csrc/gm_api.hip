@@ -379,30 +379,34 @@ __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
         rowtot += wc[k][i];
       }
       const int64_t before = off + __popcll(masks[k] & ((1ull << lane) - 1ull));
+      // (p1 < cap holds by the scan's capacity check; the test keeps every
+      // store inside the buffer whatever the offsets hold)
       if (keepv[k]) {
         const int64_t p0 = before, p1 = nk + before;
-        const int ax = A.AXIS[r] & kAxisMask;
-        double c[D], h[D];
+        if (p0 >= 0 && p1 < cap) {
+          const int ax = A.AXIS[r] & kAxisMask;
+          double c[D], h[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-          c[j] = Ci[j * cap + r];
-          h[j] = Hi[j * cap + r];
-        }
-        const uint16_t l1 = (uint16_t)(Li[r] + 1);
+          for (int j = 0; j < D; ++j) {
+            c[j] = Ci[j * cap + r];
+            h[j] = Hi[j * cap + r];
+          }
+          const uint16_t l1 = (uint16_t)(Li[r] + 1);
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-          const double hp = h[j] * 0.5;
-          const bool sp = (j == ax);
-          Co[j * cap + p0] = sp ? c[j] - hp : c[j];
-          Co[j * cap + p1] = sp ? c[j] + hp : c[j];
-          Ho[j * cap + p0] = sp ? hp : h[j];
-          Ho[j * cap + p1] = sp ? hp : h[j];
+          for (int j = 0; j < D; ++j) {
+            const double hp = h[j] * 0.5;
+            const bool sp = (j == ax);
+            Co[j * cap + p0] = sp ? c[j] - hp : c[j];
+            Co[j * cap + p1] = sp ? c[j] + hp : c[j];
+            Ho[j * cap + p0] = sp ? hp : h[j];
+            Ho[j * cap + p1] = sp ? hp : h[j];
+          }
+          Lo[p0] = l1;
+          Lo[p1] = l1;
         }
-        Lo[p0] = l1;
-        Lo[p1] = l1;
       } else if (A.LC != nullptr && r < n) {
         const int64_t slot = leaf_base + (r - before);
-        if (slot < A.leaf_cap) {
+        if (slot >= 0 && slot < A.leaf_cap) {
 #pragma unroll
           for (int j = 0; j < D; ++j) {
             A.LC[j * A.leaf_cap + slot] = Ci[j * cap + r];
@@ -902,6 +906,11 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
     GM_HIP(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     const int ran = (int)std::min<int64_t>(K, hst.iter - iter_done);
+    if (ran <= 0 && !hst.done) {
+      // the status block did not advance: never loop on it
+      g_hip_err = "internal error: the device loop made no progress";
+      return GM_EHIP;
+    }
     iter_done = hst.iter;
     if (timing) {
       for (int k = 0; k < ran; ++k) {
