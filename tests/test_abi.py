@@ -85,8 +85,25 @@ def test_options_validation():
         gm.set_option("lanes_per_region", 3)
     with pytest.raises(gm.GMError):
         gm.set_option("init_log2_regions", 31)
+    for key, bad in (("rule", 2), ("rule", -1), ("prune", 2), ("timing", 3)):
+        with pytest.raises(gm.GMError):
+            gm.set_option(key, bad)
     gm.set_option("max_iters", 10000)
     gm.set_option("init_log2_regions", 12)
+
+
+def test_gauss_kronrod_rule_validates_dimension_before_any_device_work():
+    # d = 7 is beyond the tensor-product rule's range: rejected on the host
+    gm.set_option("rule", 1)
+    try:
+        with pytest.raises(gm.GMError) as ei:
+            gm.integrate(4, np.ones(14), np.zeros(7), np.ones(7), 1e-6, 1e-16, stream=0)
+        assert ei.value.code == gm.EINVAL
+        with pytest.raises(gm.GMError) as ei:
+            gm.integrate_grad(4, np.ones(6), np.zeros(3), np.ones(3), 1e-6, 1e-16, stream=0)
+        assert ei.value.code == gm.EINVAL
+    finally:
+        gm.set_option("rule", 0)
 
 
 def test_eval_regions_rejects_bad_levels():
