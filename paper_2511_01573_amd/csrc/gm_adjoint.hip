@@ -181,12 +181,8 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(AdjArgs A) {
   for (int64_t r = (int64_t)blockIdx.x * kAdjBlock + threadIdx.x; r < A.n;
        r += (int64_t)gridDim.x * kAdjBlock) {
     double c[D], h[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      c[j] = A.C[j * A.cap + r];
-      h[j] = A.H[j * A.cap + r];
-    }
-    const double vol = ldexp(A.vol_omega, -(int)A.L[r]);
+    const int lvl = load_region<D>(A.R, r, c, h);
+    const double vol = ldexp(A.vol_omega, -lvl);
     double acc[2 * D];
 #pragma unroll
     for (int j = 0; j < 2 * D; ++j) acc[j] = 0.0;

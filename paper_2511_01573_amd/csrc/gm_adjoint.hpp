@@ -11,10 +11,7 @@ constexpr int kMaxAdjGrid = 4096;
 struct AdjArgs {
   DevParams P;
   RuleConsts K;
-  const double* C;
-  const double* H;
-  const uint16_t* L;
-  int64_t cap;
+  RegionSrc R;  // the regions (a stored split active set or the leaf store)
   int64_t n;
   double vol_omega;
   double* partials;  // [grid][2*kMaxDim][2] double-double

@@ -159,6 +159,8 @@ __global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) 
   const int prune_k = SECOND ? st->prune_k : 0;
   const bool hist_on = !SECOND && st->prune_on;
   const uint16_t* __restrict__ L = A.L[st->buf];
+  const int split = st->split;
+  const int64_t npar = st->n_par;
   const int64_t nt = (n + kTile - 1) / kTile;
   __shared__ int64_t sk[kTileThreads / 64];
   __shared__ dd sq[kTileThreads / 64], se[kTileThreads / 64];
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) 
       const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
       if (r < n) {
         const double err = A.ERR[r];
-        const int lvl = L[r];
+        const int lvl = split ? L[r >= npar ? r - npar : r] + 1 : L[r];
         bool fin = (err <= ldexp(T, -lvl)) || (aI + err == aI) || (A.AXIS[r] & 0x80);
         if (SECOND && !fin) fin = err <= ldexp(T, prune_k - lvl);
         if (hist_on && !fin) atomicAdd(&shist[prune_level(err, T, lvl)], 1u);
@@ -312,7 +314,11 @@ __global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* T
   st->leaf_count += n - total;
   st->n_prev = n;
   st->n_keep = total;
+  st->split_in = st->split;
+  st->n_par_in = st->n_par;
   st->n_active = 2 * total;
+  st->n_par = total;
+  st->split = 1;
   st->buf = 1 - st->buf;
 }
 
@@ -321,6 +327,7 @@ struct ScatterArgs {
   double* C[2];
   double* H[2];
   uint16_t* L[2];
+  uint8_t* PAX[2];
   int64_t cap;
   const uint8_t* AXIS;
   const uint8_t* FLAG;
@@ -335,22 +342,24 @@ struct ScatterArgs {
 
 // Split + stable compaction (Sec. 3: filtering and splitting fused).  Ranks
 // inside a tile come from wavefront ballots and an LDS prefix over the four
-// wavefronts; the tile's base offset comes from the scan kernel.  The
-// dimension is a template parameter so every coordinate load of a region is
-// issued before its stores.
+// wavefronts; the tile's base offset comes from the scan kernel.  Each kept
+// region is written once, at its rank p, as the record its two children are
+// read from in the next iteration (centre, half-widths, level and the split
+// axis the rule kernel chose); retired regions go to the leaf store in
+// gradient mode.  The dimension is a template parameter so every coordinate
+// load of a region is issued before its stores.
 template <int D>
 __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
   const Status* st = A.st;
   if (st->done) return;
-  const int64_t n = st->n_prev, nk = st->n_keep;
+  const int64_t n = st->n_prev;
   const int out = st->buf, in = 1 - out;
   const int64_t leaf_base = st->leaf_base;
-  const double* __restrict__ Ci = A.C[in];
-  const double* __restrict__ Hi = A.H[in];
-  const uint16_t* __restrict__ Li = A.L[in];
+  const RegionSrc R{A.C[in], A.H[in], A.L[in], A.PAX[in], A.cap, st->n_par_in, st->split_in};
   double* __restrict__ Co = A.C[out];
   double* __restrict__ Ho = A.H[out];
   uint16_t* __restrict__ Lo = A.L[out];
+  uint8_t* __restrict__ Po = A.PAX[out];
   const int64_t cap = A.cap;
   const int64_t nt = (n + kTile - 1) / kTile;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -379,40 +388,32 @@ __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
         rowtot += wc[k][i];
       }
       const int64_t before = off + __popcll(masks[k] & ((1ull << lane) - 1ull));
-      // (p1 < cap holds by the scan's capacity check; the test keeps every
+      // (p < cap / 2 holds by the scan's capacity check; the test keeps every
       // store inside the buffer whatever the offsets hold)
       if (keepv[k]) {
-        const int64_t p0 = before, p1 = nk + before;
-        if (p0 >= 0 && p1 < cap) {
-          const int ax = A.AXIS[r] & kAxisMask;
+        const int64_t p = before;
+        if (p >= 0 && p < cap) {
           double c[D], h[D];
+          const int lvl = load_region<D>(R, r, c, h);
 #pragma unroll
           for (int j = 0; j < D; ++j) {
-            c[j] = Ci[j * cap + r];
-            h[j] = Hi[j * cap + r];
+            Co[j * cap + p] = c[j];
+            Ho[j * cap + p] = h[j];
           }
-          const uint16_t l1 = (uint16_t)(Li[r] + 1);
-#pragma unroll
-          for (int j = 0; j < D; ++j) {
-            const double hp = h[j] * 0.5;
-            const bool sp = (j == ax);
-            Co[j * cap + p0] = sp ? c[j] - hp : c[j];
-            Co[j * cap + p1] = sp ? c[j] + hp : c[j];
-            Ho[j * cap + p0] = sp ? hp : h[j];
-            Ho[j * cap + p1] = sp ? hp : h[j];
-          }
-          Lo[p0] = l1;
-          Lo[p1] = l1;
+          Lo[p] = (uint16_t)lvl;
+          Po[p] = A.AXIS[r] & kAxisMask;
         }
       } else if (A.LC != nullptr && r < n) {
         const int64_t slot = leaf_base + (r - before);
         if (slot >= 0 && slot < A.leaf_cap) {
+          double c[D], h[D];
+          const int lvl = load_region<D>(R, r, c, h);
 #pragma unroll
           for (int j = 0; j < D; ++j) {
-            A.LC[j * A.leaf_cap + slot] = Ci[j * cap + r];
-            A.LH[j * A.leaf_cap + slot] = Hi[j * cap + r];
+            A.LC[j * A.leaf_cap + slot] = c[j];
+            A.LH[j * A.leaf_cap + slot] = h[j];
           }
-          A.LL[slot] = Li[r];
+          A.LL[slot] = (uint16_t)lvl;
         }
       }
       base += rowtot;
@@ -466,6 +467,8 @@ struct LastRun {
   bool valid = false;
   int d = 0;
   int64_t n = 0, cap = 0;
+  int64_t npar = 0;  // records behind a split set
+  int split = 0;
   Layout lay;
   int buf = 0;
 } g_last;
@@ -511,6 +514,7 @@ Layout make_layout(int d, int64_t cap) {
     L.C[b] = take(sizeof(double) * d * cap);
     L.H[b] = take(sizeof(double) * d * cap);
     L.L[b] = take(sizeof(uint16_t) * cap);
+    L.PAX[b] = take(cap);
   }
   L.Q = take(sizeof(double) * cap);
   L.ERR = take(sizeof(double) * cap);
@@ -774,6 +778,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
     ra.C[b] = (const double*)(base + lay.C[b]);
     ra.H[b] = (const double*)(base + lay.H[b]);
     ra.L[b] = (const uint16_t*)(base + lay.L[b]);
+    ra.PAX[b] = (const uint8_t*)(base + lay.PAX[b]);
   }
   ra.cap = cap;
   ra.Q = (double*)(base + lay.Q);
@@ -821,6 +826,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
     sa.C[b] = (double*)ra.C[b];
     sa.H[b] = (double*)ra.H[b];
     sa.L[b] = (uint16_t*)ra.L[b];
+    sa.PAX[b] = (uint8_t*)ra.PAX[b];
   }
   sa.cap = cap;
   sa.AXIS = ra.AXIS;
@@ -944,6 +950,8 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   out->E = hst.E;
   out->status = (int)hst.status;
   out->final_n = hst.n_active;
+  out->final_npar = hst.n_par;
+  out->final_split = hst.split;
   out->buf = hst.buf;
   out->leaf_count = keep_leaves ? hst.leaf_count : 0;
   out->base = base;
@@ -962,6 +970,8 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   g_last.valid = true;
   g_last.d = d;
   g_last.n = hst.n_active;
+  g_last.npar = hst.n_par;
+  g_last.split = hst.split;
   g_last.cap = cap;
   g_last.lay = lay;
   g_last.buf = hst.buf;
@@ -1064,29 +1074,51 @@ int64_t gm_last_active(int64_t offset, int64_t n, double* c, double* h, int32_t*
   const int b = g_last.buf;
   const Layout& L = g_last.lay;
   if (cnt <= 0) return g_last.n;
-  const size_t o8 = sizeof(double) * (size_t)offset;
-  std::vector<double> buf((size_t)cnt);
+  // Stored records behind regions [offset, offset + cnt): the same records when
+  // the set is not split, else the records r mod n_par (one or two ranges).
+  const bool split = g_last.split != 0;
+  const int64_t npar = g_last.npar;
+  auto rec = [&](int64_t r) { return (split && r >= npar) ? r - npar : r; };
+  int64_t q0 = rec(offset), q1 = rec(offset + cnt - 1);
+  if (split && offset < npar && offset + cnt > npar) {  // the window holds "-" and "+" children
+    q0 = 0;
+    q1 = npar - 1;
+  }
+  const int64_t nq = q1 - q0 + 1;
+  std::vector<double> pc((size_t)nq * d), ph((size_t)nq * d);
+  std::vector<uint16_t> pl((size_t)nq);
+  std::vector<uint8_t> pa((size_t)nq, 0);
   for (int j = 0; j < d; ++j) {
-    if (c) {
-      if (hipMemcpy(buf.data(), base + L.C[b] + sizeof(double) * j * g_last.cap + o8,
-                    sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
-        return hip_fail(hipGetLastError());
-      for (int64_t r = 0; r < cnt; ++r) c[r * d + j] = buf[r];
-    }
-    if (h) {
-      if (hipMemcpy(buf.data(), base + L.H[b] + sizeof(double) * j * g_last.cap + o8,
-                    sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
-        return hip_fail(hipGetLastError());
-      for (int64_t r = 0; r < cnt; ++r) h[r * d + j] = buf[r];
-    }
-  }
-  if (lvl) {
-    std::vector<uint16_t> l((size_t)cnt);
-    if (hipMemcpy(l.data(), base + L.L[b] + sizeof(uint16_t) * offset, sizeof(uint16_t) * cnt,
-                  hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(pc.data() + (size_t)j * nq, base + L.C[b] + sizeof(double) * (j * g_last.cap + q0),
+                  sizeof(double) * nq, hipMemcpyDeviceToHost) != hipSuccess)
       return hip_fail(hipGetLastError());
-    for (int64_t r = 0; r < cnt; ++r) lvl[r] = l[r];
+    if (hipMemcpy(ph.data() + (size_t)j * nq, base + L.H[b] + sizeof(double) * (j * g_last.cap + q0),
+                  sizeof(double) * nq, hipMemcpyDeviceToHost) != hipSuccess)
+      return hip_fail(hipGetLastError());
   }
+  if (hipMemcpy(pl.data(), base + L.L[b] + sizeof(uint16_t) * q0, sizeof(uint16_t) * nq,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return hip_fail(hipGetLastError());
+  if (split && hipMemcpy(pa.data(), base + L.PAX[b] + q0, nq, hipMemcpyDeviceToHost) != hipSuccess)
+    return hip_fail(hipGetLastError());
+  for (int64_t i = 0; i < cnt; ++i) {
+    const int64_t r = offset + i;
+    const int64_t k = rec(r) - q0;
+    const bool plus = split && r >= npar;
+    const int ax = pa[k];
+    for (int j = 0; j < d; ++j) {
+      double cj = pc[(size_t)j * nq + k], hj = ph[(size_t)j * nq + k];
+      if (split && j == ax) {  // the split of the Sec. 3 loop, as the device applies it
+        const double hp = hj * 0.5;
+        cj = plus ? cj + hp : cj - hp;
+        hj = hp;
+      }
+      if (c) c[i * d + j] = cj;
+      if (h) h[i * d + j] = hj;
+    }
+    if (lvl) lvl[i] = pl[k] + (split ? 1 : 0);
+  }
+  const size_t o8 = sizeof(double) * (size_t)offset;
   if (q && hipMemcpy(q, base + L.Q + o8, sizeof(double) * cnt, hipMemcpyDeviceToHost) != hipSuccess)
     return hip_fail(hipGetLastError());
   if (err &&

@@ -73,7 +73,10 @@ struct Status {
   int32_t pruned;       // pruning happened in this run
   int32_t reclassify;   // this iteration is classified again with the relaxed budget
   int32_t prune_k;      // budget factor 2^prune_k of that second pass
-  int64_t pad[2];
+  int64_t n_par;        // parent records behind a split active set
+  int32_t split;        // 1: the active set is the 2 n_par children of the stored parents
+  int32_t split_in;     // split / n_par of the set being compacted (read by the scatter)
+  int64_t n_par_in;
 };
 
 // ---------------------------------------------------------------------------
@@ -130,6 +133,55 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
+// The active set as stored.  After the first split the store holds one
+// record per region kept in the previous iteration (c, h, lvl and its split
+// axis PAX), and the active set is their 2 n_par children: region r < n_par is
+// the "-" child of record r, region n_par + r the "+" child (Sec. 3 split:
+// along the axis, c -+ h/2, h/2, level + 1 -- exact for these dyadic boxes).
+// Before the first split (and for region lists) records are the regions.
+struct RegionSrc {
+  const double* C;
+  const double* H;
+  const uint16_t* L;
+  const uint8_t* PAX;
+  int64_t cap;
+  int64_t npar;
+  int split;
+};
+
+// Region r of the active set: centre, half-widths, level.
+template <int D>
+__device__ __forceinline__ int load_region(const RegionSrc& R, int64_t r, double (&c)[D],
+                                           double (&h)[D]) {
+  const bool plus = R.split && r >= R.npar;
+  const int64_t q = plus ? r - R.npar : r;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    c[j] = R.C[j * R.cap + q];
+    h[j] = R.H[j * R.cap + q];
+  }
+  int lvl = R.L[q];
+  if (R.split) {
+    const int ax = R.PAX[q];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (j == ax) {
+        const double hp = h[j] * 0.5;
+        c[j] = plus ? c[j] + hp : c[j] - hp;
+        h[j] = hp;
+      }
+    }
+    lvl += 1;
+  }
+  return lvl;
+}
+
+// Level of region r of the active set.
+__device__ __forceinline__ int region_level(const RegionSrc& R, int64_t r) {
+  if (!R.split) return R.L[r];
+  return R.L[r >= R.npar ? r - R.npar : r] + 1;
+}
+
 // Kernel arguments of the rule kernel (Sec. 2 evaluation of every region).
 struct RuleArgs {
   DevParams P;
@@ -137,6 +189,7 @@ struct RuleArgs {
   const double* C[2];     // SoA centres  [j * cap + r], ping-pong
   const double* H[2];     // SoA half-widths
   const uint16_t* L[2];   // levels: region volume = vol_omega * 2^-lvl
+  const uint8_t* PAX[2];  // split axis of each stored record (split active sets)
   int64_t cap;
   double* Q;              // [cap] rule value
   double* ERR;            // [cap] error estimate

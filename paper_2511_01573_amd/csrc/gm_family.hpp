@@ -211,6 +211,21 @@ __device__ __forceinline__ bool active_range(const RuleArgs& A, int64_t& start, 
   return true;
 }
 
+// How the launch's regions are stored (batch stores and region lists hold
+// the regions themselves).
+template <bool BATCH>
+__device__ __forceinline__ RegionSrc region_src(const RuleArgs& A, int buf) {
+  RegionSrc R{A.C[buf], A.H[buf], A.L[buf], nullptr, A.cap, 0, 0};
+  if constexpr (!BATCH) {
+    if (A.n_fixed < 0 && A.st->split) {
+      R.split = 1;
+      R.npar = A.st->n_par;
+      R.PAX = A.PAX[buf];
+    }
+  }
+  return R;
+}
+
 template <bool BATCH>
 __device__ __forceinline__ const DevParams& region_params(const RuleArgs& A, int buf, int64_t r,
                                                          double& vol_omega) {

@@ -86,10 +86,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
   int64_t start, end;
   int buf;
   if (!active_range<false>(A, start, end, buf)) return;
-  const double* __restrict__ Cb = A.C[buf];
-  const double* __restrict__ Hb = A.H[buf];
-  const uint16_t* __restrict__ Lb = A.L[buf];
-  const int64_t cap = A.cap;
+  const RegionSrc R = region_src<false>(A, buf);
   const DevParams& P = A.P;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ double tt[kGkRegionsPerBlock][D][15];
@@ -101,10 +98,15 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
     const int64_t r = base + wv;
     const bool ok = r < end;
     double c[D], h[D];
+    int lvl = 0;
+    if (ok) {
+      lvl = load_region<D>(R, r, c, h);
+    } else {
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      c[j] = ok ? Cb[j * cap + r] : 0.0;
-      h[j] = ok ? Hb[j * cap + r] : 0.0;
+      for (int j = 0; j < D; ++j) {
+        c[j] = 0.0;
+        h[j] = 0.0;
+      }
     }
     if (ok && lane < 15) {
       const double xk = gk::kX[lane];
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
 #pragma unroll
     for (int i = 0; i < D; ++i) tm[i] = dd_val(wave_sum_dd(dd{sm[i], 0.0}));
     if (ok && lane == 0) {
-      const double vol = ldexp(A.vol_omega, -(int)Lb[r]);
+      const double vol = ldexp(A.vol_omega, -lvl);
       const double QK = dd_val(ta), QG = dd_val(tb);
       RegionResult o;
       o.q = vol * QK;

@@ -87,17 +87,15 @@ extern "C" int gm_integrate_grad(int integrand_id, const double* params, int d, 
     }
     AdjFn fn = adj_fn(d, integrand_id);
     A.partials = part;
-    A.C = lv.C;
-    A.H = lv.H;
-    A.L = lv.L;
-    A.cap = lv.cap;
+    A.R = RegionSrc{lv.C, lv.H, lv.L, nullptr, lv.cap, 0, 0};
     A.n = n1;
     hipLaunchKernelGGL(fn, dim3(g1), dim3(kAdjBlock), 0, s, A);
     A.partials = part + (size_t)g1 * 2 * kMaxDim * 2;
-    A.C = (const double*)(rr.base + rr.lay.C[rr.buf]);
-    A.H = (const double*)(rr.base + rr.lay.H[rr.buf]);
-    A.L = (const uint16_t*)(rr.base + rr.lay.L[rr.buf]);
-    A.cap = rr.cap;
+    A.R = RegionSrc{(const double*)(rr.base + rr.lay.C[rr.buf]),
+                    (const double*)(rr.base + rr.lay.H[rr.buf]),
+                    (const uint16_t*)(rr.base + rr.lay.L[rr.buf]),
+                    (const uint8_t*)(rr.base + rr.lay.PAX[rr.buf]), rr.cap, rr.final_npar,
+                    rr.final_split};
     A.n = n2;
     hipLaunchKernelGGL(fn, dim3(g2), dim3(kAdjBlock), 0, s, A);
     hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(1), dim3(64), 0, s, part, g1 + g2, 2 * d, dout);

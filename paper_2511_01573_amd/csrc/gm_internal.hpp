@@ -26,7 +26,7 @@ struct Options {
 
 // Byte offsets of the device buffers of one run inside the workspace.
 struct Layout {
-  size_t C[2], H[2], L[2];
+  size_t C[2], H[2], L[2], PAX[2];
   size_t Q, ERR, AXIS, FLAG;
   size_t TK, TOFF, TQ, TE;
   size_t PART, ST, HIST;
@@ -37,6 +37,8 @@ struct RunResult {
   double I = 0, E = 0;
   int status = 0;
   int64_t final_n = 0;
+  int64_t final_npar = 0;  // parent records behind the final set when it is split
+  int final_split = 0;
   int buf = 0;
   int64_t leaf_count = 0;
   char* base = nullptr;

@@ -270,22 +270,14 @@ void rule_tpr_kernel(RuleArgs A) {
   int64_t start, end;
   int buf;
   if (!active_range<BATCH>(A, start, end, buf)) return;
-  const double* __restrict__ Cb = A.C[buf];
-  const double* __restrict__ Hb = A.H[buf];
-  const uint16_t* __restrict__ Lb = A.L[buf];
-  const int64_t cap = A.cap;
+  const RegionSrc R = region_src<BATCH>(A, buf);
   const int64_t stride = (int64_t)gridDim.x * kRuleBlock;
   dd qs = {0.0, 0.0}, es = {0.0, 0.0};
   int nonfin = 0;
   int64_t r = start + (int64_t)blockIdx.x * kRuleBlock + threadIdx.x;
   for (; r < end; r += stride) {
     double c[D], h[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      c[j] = Cb[j * cap + r];
-      h[j] = Hb[j * cap + r];
-    }
-    const int lvl = Lb[r];
+    const int lvl = load_region<D>(R, r, c, h);
     double volo;
     const DevParams& P = region_params<BATCH>(A, buf, r, volo);
     const double vol = ldexp(volo, -lvl);
@@ -338,10 +330,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
   int64_t start, n;
   int buf;
   if (!active_range<BATCH>(A, start, n, buf)) return;
-  const double* __restrict__ Cb = A.C[buf];
-  const double* __restrict__ Hb = A.H[buf];
-  const uint16_t* __restrict__ Lb = A.L[buf];
-  const int64_t cap = A.cap;
+  const RegionSrc R = region_src<BATCH>(A, buf);
   const RuleConsts& K = A.K;
   const int g = threadIdx.x >> LOG2L;  // region slot in the block
   const int s = threadIdx.x & (L - 1);
@@ -355,10 +344,15 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
     double volo;
     const DevParams& P = region_params<BATCH>(A, buf, valid ? r : start, volo);
     double c[D], h[D];
+    int lvl = 0;
+    if (valid) {
+      lvl = load_region<D>(R, r, c, h);
+    } else {
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      c[j] = valid ? Cb[j * cap + r] : 0.5;
-      h[j] = valid ? Hb[j * cap + r] : 0.25;
+      for (int j = 0; j < D; ++j) {
+        c[j] = 0.5;
+        h[j] = 0.25;
+      }
     }
     // Per-region tables (each lane of the group writes the coordinates j = s mod L).
 #pragma unroll
@@ -447,7 +441,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
     o.err = 0.0;
     o.nonfinite = 0;
     if (s == 0 && valid) {
-      const double vol = ldexp(volo, -(int)Lb[r]);
+      const double vol = ldexp(volo, -lvl);
       rule_combine(K, f0, ks_val(S2), ks_val(S3), ks_val(S4), ks_val(S5), vol, o);
       double dmax = -1.0, scale = 0.0;
       for (int i = 0; i < D; ++i) {
