@@ -370,6 +370,231 @@ int gmo_rule(int fam, int d, const double* params, const double* c, const double
 
 
 /* ------------------------------------------------------------------------ */
+/* Degree-9 fully symmetric rule (the "9-order" Genz-Malik reading of        */
+/* Sec. 2), with the degree-7 and degree-5 rules above embedded in its nodes. */
+/*                                                                          */
+/* Generators (mean measure on [-1,1]^d, lambda values squared):             */
+/*   class 1: 0;                                                            */
+/*   class 2: +-l2 e_i (9/70);  class 3: +-l3 e_i (9/10);                    */
+/*   class 4: (+-l4, +-l4) on i < j (9/10);                                  */
+/*   class 5: (+-l5, .., +-l5) (9/19);                                       */
+/*   class 6: +-l6 e_i (759/1190);                                           */
+/*   class 7: +-l2 on i, +-l3 on j, for every ordered pair i != j;           */
+/*   class 8: (+-l4, +-l4, +-l4) on i < j < k.                               */
+/* N9(d) = 1 + 6d + 6d(d-1) + 8 C(d,3) + 2^d nodes.                          */
+/* Derivation: the even moments of degree <= 8 give 12 equations, which     */
+/* separate by the number of coordinates a monomial involves.  x^2y^2z^2w^2  */
+/* sees only the corners (fixes w5 for l5^2 = 9/19); x^2y^2z^2 and x^4y^2z^2 */
+/* then fix the triple class (its lambda comes out as 9/10 = l4^2); the four */
+/* two-coordinate moments x^2y^2, x^4y^2, x^6y^2, x^4y^4 need an asymmetric  */
+/* pair (x^6y^2 and x^4y^4 agree on every symmetric one), and their solution */
+/* puts it at (l2, l3); the one-coordinate moments x^2 .. x^8 with three     */
+/* axis classes fix l6^2 = 759/1190 and the axis weights, and the constant   */
+/* fixes w1.  The weights below are that unique solution; every monomial of */
+/* degree <= 9 is integrated exactly, x^10 is not.                          */
+/*                                                                          */
+/* Error estimates (readings: the paper names the degree and a null-rule     */
+/* heuristic but prints neither):                                           */
+/*   model 0: err = vol |Q9 - Q7|, the embedded-rule difference;             */
+/*   model 1: null-rule ratio test.  The differences of successive embedded */
+/*     rules are null rules: n1 = |Q9 - Q7| vanishes on degree <= 7,         */
+/*     n2 = |Q7 - Q5| on degree <= 5, n3 = |Q5 - Q3| on degree <= 3, with    */
+/*     Q3 = (1 - 10d/27) f(c) + 5/27 sum_i (f(c + l3 h_i e_i) + f(c - ..)),  */
+/*     the degree-3 rule on classes 1 and 3.  While they fall geometrically  */
+/*     with the degree the ratio rho = max(n1/n2, n2/n3) (both steps must     */
+/*     fall) measures the decay, and the error of Q9 is below n1 by about    */
+/*     that factor: err = vol n1 min(1, 2 rho) -- the plain difference when   */
+/*     rho >= 1/2, the difference scaled by twice the ratio below.            */
+/* Split axis: the fourth differences of classes 2 and 3, as for degree 7.   */
+/* ------------------------------------------------------------------------ */
+int64_t gmo_num_nodes9(int d) {
+  int64_t D = d;
+  return 1 + 6 * D + 6 * D * (D - 1) + 4 * D * (D - 1) * (D - 2) / 3 + ((int64_t)1 << d);
+}
+
+void gmo_constants9(int d, double lam[6], double w[8], double e[8]) {
+  int64_t D = d;
+  lam[0] = 0.0;
+  lam[1] = sqrt(9.0 / 70.0);
+  lam[2] = sqrt(9.0 / 10.0);
+  lam[3] = sqrt(9.0 / 10.0);
+  lam[4] = sqrt(9.0 / 19.0);
+  lam[5] = sqrt(759.0 / 1190.0);
+  w[0] = (double)(-160 * (6325 * D * D * D - 345345 * D * D + 1801355 * D - 1902813)) /
+         403363719.0;
+  w[1] = (double)(-490 * (2020 * D - 8711)) / 17891847.0;
+  w[2] = (double)(5 * (10400 * D * D - 236080 * D + 404019)) / 13817466.0;
+  w[3] = (double)(-1000 * (2 * D - 9)) / 531441.0;
+  w[4] = ldexp(130321.0 / 531441.0, -d);
+  w[5] = 20462645.0 / 484331562.0;
+  w[6] = 4900.0 / 177147.0;
+  w[7] = 1000.0 / 531441.0;
+  /* e = w - (degree-7 weights, 0 on classes 6..8), exact, rounded once */
+  e[0] = (double)(-8 * (126500 * D * D * D - 5882250 * D * D + 12665080 * D - 5205981)) /
+         403363719.0;
+  e[1] = (double)(-490 * (2020 * D - 3257)) / 17891847.0;
+  e[2] = (double)(5 * (10400 * D * D - 179920 * D + 148491)) / 13817466.0;
+  e[3] = (double)(-400 * (5 * D - 9)) / 531441.0;
+  e[4] = ldexp(-54872.0 / 531441.0, -d);
+  e[5] = w[5];
+  e[6] = w[6];
+  e[7] = w[7];
+}
+
+/* Node order: classes 1-5 as for degree 7, then class 6 (i ascending, + then
+   -), class 7 (i, then j != i ascending; signs (+,+), (+,-), (-,+), (-,-) on
+   (i, j)), class 8 (i < j < k lexicographic; sign pattern s = 0..7, bit 0 on
+   i, bit 1 on j, bit 2 on k, set = negative). */
+static void visit_nodes9(int d, const double* c, const double* h, node_visitor fn, void* ctx) {
+  double lam[6], w[8], e[8];
+  double x[64];
+  int i, j, k, s;
+  gmo_constants9(d, lam, w, e);
+  visit_nodes(d, c, h, fn, ctx);
+  for (k = 0; k < d; ++k) x[k] = c[k];
+  for (i = 0; i < d; ++i) {
+    x[i] = fma(lam[5], h[i], c[i]);
+    fn(ctx, 6, x);
+    x[i] = fma(-lam[5], h[i], c[i]);
+    fn(ctx, 6, x);
+    x[i] = c[i];
+  }
+  for (i = 0; i < d; ++i)
+    for (j = 0; j < d; ++j) {
+      if (j == i) continue;
+      for (s = 0; s < 4; ++s) {
+        x[i] = fma((s & 2) ? -lam[1] : lam[1], h[i], c[i]);
+        x[j] = fma((s & 1) ? -lam[2] : lam[2], h[j], c[j]);
+        fn(ctx, 7, x);
+      }
+      x[i] = c[i];
+      x[j] = c[j];
+    }
+  for (i = 0; i < d; ++i)
+    for (j = i + 1; j < d; ++j)
+      for (k = j + 1; k < d; ++k) {
+        for (s = 0; s < 8; ++s) {
+          x[i] = fma((s & 1) ? -lam[3] : lam[3], h[i], c[i]);
+          x[j] = fma((s & 2) ? -lam[3] : lam[3], h[j], c[j]);
+          x[k] = fma((s & 4) ? -lam[3] : lam[3], h[k], c[k]);
+          fn(ctx, 8, x);
+        }
+        x[i] = c[i];
+        x[j] = c[j];
+        x[k] = c[k];
+      }
+}
+
+void gmo_nodes9(int d, const double* c, const double* h, double* x, int* cls) {
+  nodes_ctx q = {d, 0, x, cls};
+  visit_nodes9(d, c, h, nodes_cb, &q);
+}
+
+typedef struct {
+  int fam, d;
+  const double* p;
+  ksum S[8];
+  double Sabs[8];
+  double f0;
+  double f2[32], f3[32];
+  int n2, n3;
+  int nonfinite;
+} rule9_ctx;
+
+static void rule9_cb(void* pp, int cls, const double* x) {
+  rule9_ctx* r = (rule9_ctx*)pp;
+  double f = gmo_f(r->fam, r->d, r->p, x);
+  if (!isfinite(f)) r->nonfinite = 1;
+  ks_add(&r->S[cls - 1], f);
+  r->Sabs[cls - 1] += fabs(f);
+  if (cls == 1) r->f0 = f;
+  if (cls == 2) r->f2[r->n2++] = f;
+  if (cls == 3) r->f3[r->n3++] = f;
+}
+
+int gmo_rule9(int fam, int d, const double* params, const double* c, const double* h, int lvl,
+              double vol_omega, int err_model, double* out) {
+  double lam[6], w[8], e[8], lam7[5], w7[5], v7[5], e7[5];
+  rule9_ctx r;
+  int k, i;
+  double S[8], vol, q, q7, n1, n2, sq, se;
+  gmo_constants9(d, lam, w, e);
+  gmo_constants(d, lam7, w7, v7, e7);
+  memset(&r, 0, sizeof r);
+  r.fam = fam;
+  r.d = d;
+  r.p = params;
+  visit_nodes9(d, c, h, rule9_cb, &r);
+  for (k = 0; k < 8; ++k) S[k] = ks_val(&r.S[k]);
+  for (k = 0; k < 8; ++k)
+    if (!isfinite(S[k])) r.nonfinite = 1;
+  vol = ldexp(vol_omega, -lvl);
+  q = w[0] * S[0];
+  for (k = 1; k < 8; ++k) q = q + w[k] * S[k];
+  q7 = w7[0] * S[0];
+  for (k = 1; k < 5; ++k) q7 = q7 + w7[k] * S[k];
+  n1 = e[0] * S[0];
+  for (k = 1; k < 8; ++k) n1 = n1 + e[k] * S[k];
+  n1 = fabs(n1);
+  n2 = e7[0] * S[0];
+  for (k = 1; k < 5; ++k) n2 = n2 + e7[k] * S[k];
+  n2 = fabs(n2);
+  sq = 0.0;
+  se = 0.0;
+  for (k = 0; k < 8; ++k) {
+    sq += fabs(w[k]) * r.Sabs[k];
+    se += fabs(e[k]) * r.Sabs[k];
+  }
+  for (k = 0; k < 5; ++k) se += fabs(e7[k]) * r.Sabs[k];
+  out[0] = vol * q;
+  {
+    /* degree-3 rule on classes 1 and 3: (1 - 10d/27) f(c) + 5/27 sum f(c +- l3 e_i) */
+    double q3 = (double)(27 - 10 * d) / 27.0 * S[0] + (5.0 / 27.0) * S[2];
+    double q5 = q7 - (e7[0] * S[0] + e7[1] * S[1] + e7[2] * S[2] + e7[3] * S[3] + e7[4] * S[4]);
+    double n3 = fabs(q5 - q3);
+    double rho = fmax(n1 / n2, n2 / n3);
+    out[9] = vol * n3;
+    out[1] = err_model ? vol * (n1 * fmin(1.0, 2.0 * rho)) : vol * n1;
+  }
+  out[4] = vol * sq;
+  out[5] = vol * se;
+  out[6] = vol * q7;
+  out[7] = vol * n1;
+  out[8] = vol * n2;
+  for (k = 0; k < 8; ++k) {
+    out[10 + k] = S[k];
+    out[18 + k] = r.Sabs[k];
+  }
+  {
+    const double r7 = 1.0 / 7.0;
+    double Dmax = -1.0, scale = 0.0, band;
+    int axis;
+    double D[32];
+    for (i = 0; i < d; ++i) {
+      double A = (r.f2[2 * i] + r.f2[2 * i + 1]) - 2.0 * r.f0;
+      double B = (r.f3[2 * i] + r.f3[2 * i + 1]) - 2.0 * r.f0;
+      double m = (fabs(r.f2[2 * i]) + fabs(r.f2[2 * i + 1]) + 2.0 * fabs(r.f0)) +
+                 r7 * (fabs(r.f3[2 * i]) + fabs(r.f3[2 * i + 1]) + 2.0 * fabs(r.f0));
+      D[i] = fabs(A - B * r7);
+      out[26 + i] = D[i];
+      if (D[i] > Dmax) Dmax = D[i];
+      if (m > scale) scale = m;
+    }
+    band = AXIS_BAND * scale;
+    axis = -1;
+    for (i = 0; i < d; ++i)
+      if (D[i] >= Dmax - band && (axis < 0 || h[i] > h[axis])) axis = i;
+    out[2] = (double)axis;
+    {
+      double hp = h[axis] * 0.5;
+      int geo = (c[axis] - hp == c[axis]) || (c[axis] + hp == c[axis]) || (hp == 0.0);
+      out[3] = geo ? 1.0 : 0.0;
+    }
+  }
+  return r.nonfinite ? GMO_NONFINITE : 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tensor-product Gauss-Kronrod rule (Sec. 3: the framework's second rule,  */
 /* "a tensor-product Gauss-Kronrod rule [Kronrod 1965]").                    */
 /*                                                                          */
@@ -662,7 +887,8 @@ int gmo_rule_gk(int fam, int d, const double* params, const double* c, const dou
 /* ------------------------------------------------------------------------ */
 struct gmo_run {
   int fam, d, max_iters, keep_leaves;
-  int rule; /* 0 Genz-Malik, 1 tensor-product Gauss-Kronrod */
+  int rule; /* 0 Genz-Malik degree 7, 1 tensor-product Gauss-Kronrod, 2 degree 9 */
+  int err_model; /* degree-9 rule: 0 |Q9 - Q7|, 1 null-rule ratio test */
   int prune, pruned; /* memory-pressure pruning: enabled, happened */
   double params[32];
   double rel_tol, abs_tol, vol_omega;
@@ -808,14 +1034,22 @@ static int phase_eval(gmo_run* r) {
   r->iter++;
   r->stats[GMO_ST_ITERS] = r->iter;
   r->stats[GMO_ST_REGIONS] += r->n;
-  r->stats[GMO_ST_EVALS] += r->n * (r->rule ? gmo_gk_num_nodes(d) : gmo_num_nodes(d));
+  r->stats[GMO_ST_EVALS] += r->n * (r->rule == 1   ? gmo_gk_num_nodes(d)
+                                     : r->rule == 2 ? gmo_num_nodes9(d)
+                                                    : gmo_num_nodes(d));
   r->stats[GMO_ST_ACTIVE] = r->n;
   if (r->n > r->stats[GMO_ST_MAX_ACTIVE]) r->stats[GMO_ST_MAX_ACTIVE] = r->n;
   for (i = 0; i < r->n; ++i) {
-    int rc = r->rule ? gmo_rule_gk(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i],
-                                   r->vol_omega, out)
-                     : gmo_rule(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i],
-                                r->vol_omega, out);
+    int rc;
+    if (r->rule == 1)
+      rc = gmo_rule_gk(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
+                       out);
+    else if (r->rule == 2)
+      rc = gmo_rule9(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
+                     r->err_model, out);
+    else
+      rc = gmo_rule(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
+                    out);
     if (rc == GMO_NONFINITE) {
       r->I = NAN;
       r->E = NAN;
@@ -968,8 +1202,14 @@ static int phase_split(gmo_run* r) {
 }
 
 int gmo_set_rule(gmo_run* r, int rule) {
-  if (rule < 0 || rule > 1 || (rule == 1 && r->d > 6) || r->iter > 0) return GMO_EINVAL;
+  if (rule < 0 || rule > 2 || (rule == 1 && r->d > 6) || r->iter > 0) return GMO_EINVAL;
   r->rule = rule;
+  return GMO_OK;
+}
+
+int gmo_set_err_model(gmo_run* r, int model) {
+  if (model < 0 || model > 1 || r->iter > 0) return GMO_EINVAL;
+  r->err_model = model;
   return GMO_OK;
 }
 

@@ -19,7 +19,9 @@
  *   - the derivative of the fixed-tree quadrature with respect to the
  *     integrand parameters, and a lock-step batch of independent integrals;
  *   - the tensor-product Gauss-Kronrod rule the framework offers besides
- *     the Genz-Malik rule (Sec. 3), for d <= 6.
+ *     the Genz-Malik rule (Sec. 3), for d <= 6;
+ *   - a degree-9 fully symmetric rule (the "9-order" reading of Sec. 2)
+ *     with the degree-7 rule embedded, and a null-rule error heuristic.
  *
  * All floating point is IEEE binary64, built with -ffp-contract=off; every
  * fused multiply-add is written out as fma().
@@ -82,6 +84,20 @@ int64_t gmo_gk_num_nodes(int d);
    S[0] = K-sum, S[1] = G-sum and D[i] = the one-axis estimates e_i. */
 int gmo_rule_gk(int fam, int d, const double* params, const double* c, const double* h, int lvl,
                 double vol_omega, double* out);
+/* Degree-9 fully symmetric rule with the degree-7 and degree-5 rules
+   embedded (classes 1..8, see gm_oracle.c).  lam[6] = {0, l2, l3, l4, l5, l6};
+   w[8] the degree-9 weights, e[8] = w minus the degree-7 weights. */
+int64_t gmo_num_nodes9(int d);
+void gmo_constants9(int d, double lam[6], double w[8], double e[8]);
+/* All N9(d) nodes in visit order: x[N*d], cls[N] in 1..8. */
+void gmo_nodes9(int d, const double* c, const double* h, double* x, int* cls);
+/* One region with the degree-9 rule.  out layout (double):
+ *   [0] Q9  [1] err (model 0: vol |Q9 - Q7|; 1: null-rule ratio test)
+ *   [2] axis  [3] geometry flag  [4] scaleQ  [5] scaleE
+ *   [6] Q7  [7] n1 = vol |Q9 - Q7|  [8] n2 = vol |Q7 - Q5|  [9] n3 = vol |Q5 - Q3|
+ *   [10..18) S_1..S_8  [18..26) Sabs_1..Sabs_8  [26..26+d) D_0..D_{d-1} */
+int gmo_rule9(int fam, int d, const double* params, const double* c, const double* h, int lvl,
+              double vol_omega, int err_model, double* out);
 /* Integrand value at x; params = a[0..d), u[0..d). */
 double gmo_f(int fam, int d, const double* params, const double* x);
 /* Gradient of f at x with respect to params (out[2d]); returns f. */
@@ -105,9 +121,13 @@ gmo_run* gmo_create(int fam, int d, const double* params, const double* lo, cons
                     double rel_tol, double abs_tol, int64_t max_regions, int init_log2,
                     int max_iters, int keep_leaves, int* status);
 /* One full iteration; returns GMO_RUNNING or the final status. */
-/* Select the rule of a run before its first step: 0 Genz-Malik (default),
-   1 tensor-product Gauss-Kronrod (2 <= d <= 6).  GMO_EINVAL otherwise. */
+/* Select the rule of a run before its first step: 0 Genz-Malik degree 7
+   (default), 1 tensor-product Gauss-Kronrod (2 <= d <= 6), 2 degree-9 fully
+   symmetric rule.  GMO_EINVAL otherwise. */
 int gmo_set_rule(gmo_run* r, int rule);
+/* Error model of the degree-9 rule (before the first step): 0 |Q9 - Q7|,
+   1 null-rule ratio test. */
+int gmo_set_err_model(gmo_run* r, int model);
 /* Memory-pressure pruning (before the first step): when the kept regions would
    overflow the capacity, relax the classifier's budget by the smallest power
    of two that makes them fit and continue.  gmo_pruned: whether it happened. */

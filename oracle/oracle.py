@@ -99,6 +99,14 @@ def lib():
         L.gmo_rule_gk.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int, C.c_double, dp]
         L.gmo_set_rule.restype = C.c_int
         L.gmo_set_rule.argtypes = [C.c_void_p, C.c_int]
+        L.gmo_set_err_model.restype = C.c_int
+        L.gmo_set_err_model.argtypes = [C.c_void_p, C.c_int]
+        L.gmo_num_nodes9.restype = C.c_int64
+        L.gmo_num_nodes9.argtypes = [C.c_int]
+        L.gmo_constants9.argtypes = [C.c_int, dp, dp, dp]
+        L.gmo_nodes9.argtypes = [C.c_int, dp, dp, dp, ip]
+        L.gmo_rule9.restype = C.c_int
+        L.gmo_rule9.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int, C.c_double, C.c_int, dp]
         L.gmo_set_prune.restype = C.c_int
         L.gmo_set_prune.argtypes = [C.c_void_p, C.c_int]
         L.gmo_pruned.restype = C.c_int
@@ -162,7 +170,31 @@ def df(fam: int, params, x):
     return float(val), out
 
 
-GENZ_MALIK, GAUSS_KRONROD = 0, 1
+GENZ_MALIK, GAUSS_KRONROD, DEGREE9 = 0, 1, 2
+
+
+def num_nodes9(d: int) -> int:
+    return int(lib().gmo_num_nodes9(d))
+
+
+def constants9(d: int):
+    """(lam[6], w[8], e[8]) of the degree-9 rule: lam = (0, l2, l3, l4, l5, l6),
+    w the weights of classes 1..8, e = w minus the embedded degree-7 weights."""
+    lam, w, e = np.zeros(6), np.zeros(8), np.zeros(8)
+    lib().gmo_constants9(d, _d(lam)[1], _d(w)[1], _d(e)[1])
+    return lam, w, e
+
+
+def nodes9(d: int, c, h):
+    """All nodes of the degree-9 rule on region (c, h) in visit order."""
+    n = num_nodes9(d)
+    x = np.zeros((n, d))
+    cls = np.zeros(n, dtype=np.intc)
+    c, cp = _d(c)
+    h, hp = _d(h)
+    lib().gmo_nodes9(d, cp, hp, x.ctypes.data_as(C.POINTER(C.c_double)),
+                     cls.ctypes.data_as(C.POINTER(C.c_int)))
+    return x, cls
 
 
 def gk_constants():
@@ -176,13 +208,19 @@ def gk_num_nodes(d: int) -> int:
     return int(lib().gmo_gk_num_nodes(d))
 
 
-def _rule_fn(rule_id: int):
+def _rule_fn(rule_id: int, err_model: int = 0):
+    if rule_id == DEGREE9:
+        return lambda fam, d, pp, cp, hp, lvl, vo, op: lib().gmo_rule9(fam, d, pp, cp, hp, lvl, vo,
+                                                                       int(err_model), op)
     return lib().gmo_rule_gk if rule_id == GAUSS_KRONROD else lib().gmo_rule
 
 
-def rule(fam: int, params, c, h, lvl: int = 0, vol_omega: float | None = None, rule_id: int = 0):
+def rule(fam: int, params, c, h, lvl: int = 0, vol_omega: float | None = None, rule_id: int = 0,
+         err_model: int = 0):
     """One region (c, h, lvl); returns a dict with Q, err, axis, geo, scales, S, Sabs, D
-    (Gauss-Kronrod rule: S[0], S[1] = K and G sums, D = one-axis estimates)."""
+    (Gauss-Kronrod rule: S[0], S[1] = K and G sums, D = one-axis estimates; degree-9
+    rule: eight class sums and also Q7 and the null-rule values n1 = vol |Q9 - Q7|,
+    n2 = vol |Q7 - Q5|, n3 = vol |Q5 - Q3|)."""
     c, cp = _d(c)
     h, hp = _d(h)
     d = c.size
@@ -191,15 +229,18 @@ def rule(fam: int, params, c, h, lvl: int = 0, vol_omega: float | None = None, r
         # region volume = prod 2h when lvl == 0
         vol_omega = float(np.prod(2.0 * h))
     out = np.zeros(16 + 32)
-    rc = _rule_fn(rule_id)(fam, d, pp, cp, hp, int(lvl), float(vol_omega), _d(out)[1])
-    return {
-        "status": rc, "Q": out[0], "err": out[1], "axis": int(out[2]), "geo": int(out[3]),
-        "scaleQ": out[4], "scaleE": out[5], "S": out[6:11].copy(), "Sabs": out[11:16].copy(),
-        "D": out[16:16 + d].copy(),
-    }
+    rc = _rule_fn(rule_id, err_model)(fam, d, pp, cp, hp, int(lvl), float(vol_omega), _d(out)[1])
+    res = {"status": rc, "Q": out[0], "err": out[1], "axis": int(out[2]), "geo": int(out[3]),
+           "scaleQ": out[4], "scaleE": out[5]}
+    if rule_id == DEGREE9:
+        res.update({"Q7": out[6], "n1": out[7], "n2": out[8], "n3": out[9], "S": out[10:18].copy(),
+                    "Sabs": out[18:26].copy(), "D": out[26:26 + d].copy()})
+    else:
+        res.update({"S": out[6:11].copy(), "Sabs": out[11:16].copy(), "D": out[16:16 + d].copy()})
+    return res
 
 
-def rule_many(fam: int, params, c, h, lvl, vol_omega: float, rule_id: int = 0):
+def rule_many(fam: int, params, c, h, lvl, vol_omega: float, rule_id: int = 0, err_model: int = 0):
     """Rule on a list of regions; c, h: [n, d]; returns dict of arrays."""
     c = np.ascontiguousarray(c, dtype=np.float64)
     h = np.ascontiguousarray(h, dtype=np.float64)
@@ -211,7 +252,7 @@ def rule_many(fam: int, params, c, h, lvl, vol_omega: float, rule_id: int = 0):
     res["axis"] = np.zeros(n, dtype=np.int32)
     res["geo"] = np.zeros(n, dtype=np.int32)
     res["status"] = np.zeros(n, dtype=np.int32)
-    fn = _rule_fn(rule_id)
+    fn = _rule_fn(rule_id, err_model)
     for i in range(n):
         ci = c[i]
         hi = h[i]
@@ -231,7 +272,8 @@ class Run:
     """Handle on one adaptive run of the oracle (Sec. 3 loop)."""
 
     def __init__(self, fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20,
-                 init_log2=12, max_iters=10000, keep_leaves=False, rule_id=0, prune=False):
+                 init_log2=12, max_iters=10000, keep_leaves=False, rule_id=0, prune=False,
+                 err_model=0):
         self.fam = fam
         self.params, pp = _d(params)
         self.lo, lp = _d(lo)
@@ -246,6 +288,8 @@ class Run:
             raise ValueError(f"oracle rejected arguments (status {st.value})")
         if rule_id and lib().gmo_set_rule(self.h, int(rule_id)) != OK:
             raise ValueError(f"oracle rejected rule {rule_id} at d = {self.d}")
+        if err_model and lib().gmo_set_err_model(self.h, int(err_model)) != OK:
+            raise ValueError(f"oracle rejected error model {err_model}")
         if prune:
             lib().gmo_set_prune(self.h, 1)
         self.vol_omega = float(np.prod(self.hi - self.lo)) if self.d else 1.0
@@ -313,9 +357,9 @@ class Run:
 
 
 def integrate(fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20, init_log2=12,
-              max_iters=10000, rule_id=0, prune=False):
+              max_iters=10000, rule_id=0, prune=False, err_model=0):
     r = Run(fam, params, lo, hi, rel_tol, abs_tol, max_regions, init_log2, max_iters,
-            rule_id=rule_id, prune=prune)
+            rule_id=rule_id, prune=prune, err_model=err_model)
     r.run()
     return r.result()
 
