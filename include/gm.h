@@ -162,7 +162,19 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  *                        err = vol |Q_K - Q_G|), for gm_integrate and
  *                        gm_eval_regions with 2 <= d <= 6 (GM_EINVAL above;
  *                        gm_integrate_batch and gm_integrate_grad return
- *                        GM_EINVAL while it is selected)
+ *                        GM_EINVAL while it is selected); 2 = the degree-9
+ *                        fully symmetric rule (the "9-order" rule of Sec. 2,
+ *                        read as degree 9 with the degree-7 and degree-5
+ *                        Genz-Malik rules embedded: 1 + 6d + 6d(d-1) +
+ *                        8 C(d,3) + 2^d nodes, error estimate per
+ *                        "err_model"), for gm_integrate and gm_eval_regions
+ *                        with 2 <= d <= 16 (batch and gradient: GM_EINVAL)
+ *   "err_model"          error estimate of the degree-9 rule: 0 = vol |Q9 - Q7|
+ *                        (default); 1 = the null-rule ratio test of Sec. 2's
+ *                        heuristic-estimator reading: with n1 = |Q9 - Q7|,
+ *                        n2 = |Q7 - Q5|, n3 = |Q5 - Q3| (Q3 the degree-3 rule
+ *                        on the centre and the +-l3 e_i nodes),
+ *                        err = vol n1 min(1, 2 max(n1/n2, n2/n3))
  *   "prune"              1 = memory-pressure pruning: when the kept regions would
  *                        overflow max_regions, relax the classifier's budget
  *                        (err <= T 2^-lvl) by the smallest power of two 2^k,

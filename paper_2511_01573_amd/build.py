@@ -1,6 +1,6 @@
 """Build libgm.so (HIP, gfx950) in-tree.
 
-The rule (Genz-Malik and Gauss-Kronrod) and adjoint kernels are compiled once per integrand family
+The rule (Genz-Malik degree 7 and 9, Gauss-Kronrod) and adjoint kernels are compiled once per integrand family
 (-DGM_RULE_FAMILY=k / -DGM_FAMILY=k) so the objects build in parallel; everything links into
 paper_2511_01573_amd/libgm.so.  Flags: FP64 code with no implicit FMA
 contraction (-ffp-contract=off; fused multiply-adds are written explicitly),
@@ -28,7 +28,7 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-ffp-contract=off", "-f
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 FAMILIES = range(1, 8)
 # translation units compiled once per integrand family (template-heavy kernels)
-PER_FAMILY = ("gm_rule", "gm_adjoint", "gm_gk")
+PER_FAMILY = ("gm_rule", "gm_rule9", "gm_adjoint", "gm_gk")
 
 
 def _units():

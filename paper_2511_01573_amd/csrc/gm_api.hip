@@ -575,6 +575,32 @@ void fill_consts(int d, RuleConsts& K) {
   K.e[4] = K.w[4];
   K.r7 = 1.0 / 7.0;
   K.axis_band = 1e-10;
+  // degree-9 rule: the unique solution of its even-moment equations (degree
+  // <= 8), each weight one correctly rounded division of exact integers
+  K.lam6 = std::sqrt(759.0 / 1190.0);
+  K.w9[0] = (double)(-160 * (6325 * D * D * D - 345345 * D * D + 1801355 * D - 1902813)) /
+            403363719.0;
+  K.w9[1] = (double)(-490 * (2020 * D - 8711)) / 17891847.0;
+  K.w9[2] = (double)(5 * (10400 * D * D - 236080 * D + 404019)) / 13817466.0;
+  K.w9[3] = (double)(-1000 * (2 * D - 9)) / 531441.0;
+  K.w9[4] = std::ldexp(130321.0 / 531441.0, -d);
+  K.w9[5] = 20462645.0 / 484331562.0;
+  K.w9[6] = 4900.0 / 177147.0;
+  K.w9[7] = 1000.0 / 531441.0;
+  // minus the degree-7 weights (zero on classes 6..8), exact, rounded once
+  K.e9[0] = (double)(-8 * (126500 * D * D * D - 5882250 * D * D + 12665080 * D - 5205981)) /
+            403363719.0;
+  K.e9[1] = (double)(-490 * (2020 * D - 3257)) / 17891847.0;
+  K.e9[2] = (double)(5 * (10400 * D * D - 179920 * D + 148491)) / 13817466.0;
+  K.e9[3] = (double)(-400 * (5 * D - 9)) / 531441.0;
+  K.e9[4] = std::ldexp(-54872.0 / 531441.0, -d);
+  K.e9[5] = K.w9[5];
+  K.e9[6] = K.w9[6];
+  K.e9[7] = K.w9[7];
+  // degree-3 rule on the centre and the +-l3 e_i nodes (exact on 1 and x^2)
+  K.q3[0] = (double)(27 - 10 * D) / 27.0;
+  K.q3[1] = 5.0 / 27.0;
+  K.err_model = g_opt.err_model;
 }
 
 void fill_params(int fam, int d, const double* params, DevParams& P) {
@@ -633,8 +659,27 @@ RuleKernelFn gk_kernel(int d, int fam) {
   }
 }
 
-// Mapping code of the Gauss-Kronrod kernel (one wavefront per region).
+RuleKernelFn r9_kernel(int d, int fam) {
+  switch (fam) {
+    case 1: return rule9_kernel_f1(d);
+    case 2: return rule9_kernel_f2(d);
+    case 3: return rule9_kernel_f3(d);
+    case 4: return rule9_kernel_f4(d);
+    case 5: return rule9_kernel_f5(d);
+    case 6: return rule9_kernel_f6(d);
+    case 7: return rule9_kernel_f7(d);
+    default: return nullptr;
+  }
+}
+
+// Mapping codes: the Gauss-Kronrod kernel (one wavefront per region), and the
+// degree-9 kernel with 2^(code - kMapR9) lanes per region.
 constexpr int kMapGk = 100;
+constexpr int kMapR9 = 200;
+
+int lanes_of_mapping(int map) {
+  return map == kMapGk ? 64 : map >= kMapR9 ? (1 << (map - kMapR9)) : map < 0 ? 1 : (1 << map);
+}
 
 int64_t nodes_per_region(int d) {
   if (g_opt.rule == 1) {
@@ -642,11 +687,17 @@ int64_t nodes_per_region(int d) {
     for (int j = 0; j < d; ++j) n *= 15;
     return n;
   }
+  if (g_opt.rule == 2) {
+    const int64_t D = d;
+    return 1 + 6 * D + 6 * D * (D - 1) + 4 * D * (D - 1) * (D - 2) / 3 + ((int64_t)1 << d);
+  }
   return gm_num_nodes(d);
 }
 
 hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s) {
-  RuleKernelFn fn = log2l == kMapGk ? gk_kernel(d, fam) : rule_kernel(d, fam, log2l, false);
+  RuleKernelFn fn = log2l == kMapGk    ? gk_kernel(d, fam)
+                    : log2l >= kMapR9 ? r9_kernel(d, fam)
+                                      : rule_kernel(d, fam, log2l, false);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kRuleBlockSize), 0, s, a);
   return hipGetLastError();
@@ -665,6 +716,7 @@ constexpr int64_t kTargetLanes = 131072;
 
 int choose_mapping(int d, int64_t n) {
   if (g_opt.rule == 1) return kMapGk;
+  if (g_opt.rule == 2) return kMapR9 + rule9_log2l(d);
   const int forced = g_opt.lanes_per_region;
   if (forced > 0) {
     int l = -1;
@@ -687,7 +739,8 @@ int choose_mapping(int d, int64_t n) {
 }
 
 int rule_grid(int log2l, int64_t n) {
-  const int64_t per_block = log2l == kMapGk ? kRuleBlockSize / 64
+  const int64_t per_block = log2l == kMapGk    ? kRuleBlockSize / 64
+                            : log2l >= kMapR9 ? (kRuleBlockSize >> (log2l - kMapR9))
                             : (log2l < 0)   ? kRuleBlockSize
                                             : (kRuleBlockSize >> log2l);
   const int64_t g = (n + per_block - 1) / per_block;
@@ -884,7 +937,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       const int map = choose_mapping(d, nb);
       const int rg = rule_grid(map, nb);
       const int tg = tile_grid_for(nb);
-      g_stats.lanes_per_region = map == kMapGk ? 64 : map < 0 ? 1 : (1 << map);
+      g_stats.lanes_per_region = lanes_of_mapping(map);
       if (timing) GM_HIP(hipEventRecord(ev[k][0], s));
       GM_HIP(launch_rule(d, fam, map, ra, rg, s));
       if (timing) GM_HIP(hipEventRecord(ev[k][1], s));
@@ -1172,8 +1225,11 @@ int gm_set_option(const char* key, int64_t value) {
     if (value < 0 || value > 2) return GM_EINVAL;
     g_opt.timing = (int)value;
   } else if (k == "rule") {
-    if (value < 0 || value > 1) return GM_EINVAL;
+    if (value < 0 || value > 2) return GM_EINVAL;
     g_opt.rule = (int)value;
+  } else if (k == "err_model") {
+    if (value < 0 || value > 1) return GM_EINVAL;
+    g_opt.err_model = (int)value;
   } else if (k == "prune") {
     if (value < 0 || value > 1) return GM_EINVAL;
     g_opt.prune = (int)value;

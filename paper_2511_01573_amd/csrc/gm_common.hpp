@@ -47,6 +47,13 @@ struct RuleConsts {
   double e[5];
   double r7;
   double axis_band;  // relative noise band of the split-axis comparison
+  // Degree-9 rule (classes 1..8: the five above, +-l6 e_i, (+-l2 e_i, +-l3 e_j)
+  // for ordered pairs i != j, +-l4 (e_i + e_j + e_k) for i < j < k).
+  double lam6;
+  double w9[8];   // degree-9 weights
+  double e9[8];   // degree-9 minus degree-7 weights
+  double q3[2];   // degree-3 rule on the centre and the +-l3 e_i nodes
+  int32_t err_model;  // 0: |Q9 - Q7|; 1: null-rule ratio test
 };
 
 // Device status block: the only state the host reads between iterations.
@@ -238,5 +245,17 @@ RuleKernelFn gk_kernel_f5(int d);
 RuleKernelFn gk_kernel_f6(int d);
 RuleKernelFn gk_kernel_f7(int d);
 constexpr int kGkMaxDim = 6;
+
+// Degree-9 fully symmetric rule kernels, one launcher per family, 2 <= d <= 16;
+// 2^rule9_log2l(d) lanes of one wavefront per region (at least one corner and
+// at most 64 lanes per region).
+RuleKernelFn rule9_kernel_f1(int d);
+RuleKernelFn rule9_kernel_f2(int d);
+RuleKernelFn rule9_kernel_f3(int d);
+RuleKernelFn rule9_kernel_f4(int d);
+RuleKernelFn rule9_kernel_f5(int d);
+RuleKernelFn rule9_kernel_f6(int d);
+RuleKernelFn rule9_kernel_f7(int d);
+constexpr int rule9_log2l(int d) { return d - 4 < 2 ? 2 : (d - 4 > 6 ? 6 : d - 4); }
 
 }  // namespace gm

@@ -20,7 +20,9 @@ struct Options {
   int lanes_per_region = 0;  // rule-kernel mapping (0 = automatic)
   int timing = 0;            // per-phase hipEvent timing
   int log = 0;               // per-iteration log to stderr
-  int rule = 0;              // 0 Genz-Malik, 1 tensor-product Gauss-Kronrod (d <= 6)
+  int rule = 0;              // 0 Genz-Malik degree 7, 1 tensor-product Gauss-Kronrod
+                             // (d <= 6), 2 degree-9 fully symmetric rule
+  int err_model = 0;         // degree-9 rule: 0 |Q9 - Q7|, 1 null-rule ratio test
   int prune = 0;             // memory-pressure pruning instead of stopping at capacity
 };
 

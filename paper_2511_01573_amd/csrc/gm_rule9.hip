@@ -1,0 +1,325 @@
+// gm_rule9.hip -- the degree-9 rule kernel: the fully symmetric rule of degree
+// 9 (the "9-order" reading of arXiv 2511.01573, Sec. 2) with the degree-7 and
+// degree-5 Genz-Malik rules embedded in its nodes, its error estimate and the
+// fourth-difference split axis, on every active region (Sec. 3 evaluate step).
+//
+// Rule (mean measure on [-1,1]^d, lambda^2 in brackets):
+//   class 1  centre                                weight w9_1(d)
+//   class 2  +-l2 e_i                 (9/70)       w9_2(d)
+//   class 3  +-l3 e_i                 (9/10)       w9_3(d)
+//   class 4  +-l4 e_i +- l4 e_j, i<j  (9/10)       w9_4(d)
+//   class 5  (+-l5, .., +-l5)         (9/19)       w9_5 2^-d
+//   class 6  +-l6 e_i                 (759/1190)   w9_6
+//   class 7  +-l2 e_i +- l3 e_j, i != j            w9_7
+//   class 8  +-l4 (e_i +- e_j +- e_k), i<j<k       w9_8
+// (the weights are the unique solution of the even-moment equations of degree
+// <= 8 for these generators).  Classes 1-5 with the degree-7 weights give Q7;
+// with the degree-5 weights Q5; classes 1 and 3 with (1 - 10d/27, 5/27) give a
+// degree-3 rule Q3.  err = vol |Q9 - Q7| (model 0), or the null-rule ratio
+// test vol n1 min(1, 2 max(n1/n2, n2/n3)) with n1 = |Q9 - Q7|, n2 = |Q7 - Q5|,
+// n3 = |Q5 - Q3| (model 1).  Split axis: the degree-7 rule's fourth
+// differences of classes 2 and 3.
+//
+// Mapping: L = 2^rule9_log2l(d) lanes of one wavefront per region.  Lane s
+// fixes the signs of the first log2 L corner coordinates and sweeps its
+// 2^(d - log2 L) corners as a binary tree; the O(d^3) nodes of the other
+// classes are dealt out as work items (an axis: its 6 nodes and its fourth
+// difference; an axis pair: 4 class-4 and 8 class-7 nodes; an axis triple: 8
+// class-8 nodes).  Every node argument is the left-to-right chain of the
+// per-coordinate terms, as in the degree-7 kernel, so node values match the
+// defining formula's evaluation order bitwise.
+#include "gm_corner.hpp"
+
+namespace gm {
+
+template <int D>
+struct R9Slot {
+  double c[D], h[D], tc[D], pc[D], dv[D], sc[D];
+};
+
+// The (i, j, k) triple with lexicographic index p, i < j < k < D.
+template <int D>
+__device__ __forceinline__ void triple_of(int p, int& i, int& j, int& k) {
+  i = 0;
+  int cnt = (D - 1) * (D - 2) / 2;  // triples whose first index is i
+  while (p >= cnt) {
+    p -= cnt;
+    ++i;
+    cnt = (D - 1 - i) * (D - 2 - i) / 2;
+  }
+  j = i + 1;
+  int row = D - 1 - j;  // triples (i, j, k) with this j
+  while (p >= row) {
+    p -= row;
+    ++j;
+    --row;
+  }
+  k = j + 1 + p;
+}
+
+// Chain of centre terms over coordinates k0 .. k1-1 below s.
+template <int FAM>
+__device__ __forceinline__ double chain_mid(double s, const double* tc, int k0, int k1) {
+  for (int k = k0; k < k1; ++k) s = Fam<FAM>::comb(s, tc[k]);
+  return s;
+}
+
+template <int D, int FAM, int LOG2L>
+__global__ __launch_bounds__(kRuleBlock) void rule9_kernel(RuleArgs A) {
+  using F = Fam<FAM>;
+  constexpr int L = 1 << LOG2L;
+  constexpr int RPB = kRuleBlock / L;  // regions per block step
+  constexpr int NPAIR = D * (D - 1) / 2;
+  constexpr int NTRI = D * (D - 1) * (D - 2) / 6;
+  constexpr int NITEM = D + NPAIR + NTRI;
+  static_assert(LOG2L <= D && LOG2L <= 6, "at least one corner and one wavefront per region");
+  __shared__ R9Slot<D> slots[RPB];
+  int64_t start, n;
+  int buf;
+  if (!active_range<false>(A, start, n, buf)) return;
+  const RegionSrc R = region_src<false>(A, buf);
+  const RuleConsts& K = A.K;
+  const DevParams& P = A.P;
+  const int g = threadIdx.x >> LOG2L;  // region slot in the block
+  const int s = threadIdx.x & (L - 1);
+  R9Slot<D>& sl = slots[g];
+  dd qs = {0.0, 0.0}, es = {0.0, 0.0};
+  int nonfin = 0;
+  for (int64_t base = start + (int64_t)blockIdx.x * RPB; base < n;
+       base += (int64_t)gridDim.x * RPB) {
+    const int64_t r = base + g;
+    const bool valid = r < n;
+    double c[D], h[D];
+    int lvl = 0;
+    if (valid) {
+      lvl = load_region<D>(R, r, c, h);
+    } else {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        c[j] = 0.5;
+        h[j] = 0.25;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if ((j & (L - 1)) == s) {
+        sl.c[j] = c[j];
+        sl.h[j] = h[j];
+      }
+    }
+    double tc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) tc[j] = F::term(P, j, c[j]);
+    double pc = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      if ((k & (L - 1)) == s) {
+        sl.tc[k] = tc[k];
+        sl.pc[k] = pc;
+      }
+      pc = (k == 0) ? tc[0] : F::comb(pc, tc[k]);
+    }
+    __syncthreads();
+    const double f0 = F::template outer<D>(P, pc);
+    KSum S2 = {0.0, 0.0}, S3 = {0.0, 0.0}, S4 = {0.0, 0.0}, S5 = {0.0, 0.0};
+    KSum S6 = {0.0, 0.0}, S7 = {0.0, 0.0}, S8 = {0.0, 0.0};
+    for (int it = s; it < NITEM; it += L) {
+      if (it < D) {
+        // axis i: +-l2, +-l3, +-l6 and the fourth difference
+        const int i = it;
+        const double ci = sl.c[i], hi = sl.h[i];
+        const double v[6] = {F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci)),
+                             F::term(P, i, fma(K.lam3, hi, ci)), F::term(P, i, fma(-K.lam3, hi, ci)),
+                             F::term(P, i, fma(K.lam6, hi, ci)), F::term(P, i, fma(-K.lam6, hi, ci))};
+        const double pci = sl.pc[i];
+        double f[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const double s0 = (i == 0) ? v[q] : F::comb(pci, v[q]);
+          f[q] = F::template outer<D>(P, chain_tail<D, FAM>(s0, sl.tc, i + 1));
+        }
+        ks_add(S2, f[0]);
+        ks_add(S2, f[1]);
+        ks_add(S3, f[2]);
+        ks_add(S3, f[3]);
+        ks_add(S6, f[4]);
+        ks_add(S6, f[5]);
+        double dv, scv;
+        fourth_diff(K, f0, f[0], f[1], f[2], f[3], dv, scv);
+        sl.dv[i] = dv;
+        sl.sc[i] = scv;
+      } else if (it < D + NPAIR) {
+        // axis pair i < j: class 4 (+-l4, +-l4) and class 7 in both orders
+        int i, j;
+        pair_of<D>(it - D, i, j);
+        const double ci = sl.c[i], hi = sl.h[i], cj = sl.c[j], hj = sl.h[j];
+        // x_i at +l3, -l3 (= +-l4), +l2, -l2
+        const double ti[4] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci)),
+                              F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci))};
+        const double tj3[2] = {F::term(P, j, fma(K.lam4, hj, cj)),
+                               F::term(P, j, fma(-K.lam4, hj, cj))};
+        const double tj2[2] = {F::term(P, j, fma(K.lam2, hj, cj)),
+                               F::term(P, j, fma(-K.lam2, hj, cj))};
+        const double pci = sl.pc[i];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const double m =
+              chain_mid<FAM>((i == 0) ? ti[a] : F::comb(pci, ti[a]), sl.tc, i + 1, j);
+#pragma unroll
+          for (int sj = 0; sj < 2; ++sj) {
+            const double x3 =
+                F::template outer<D>(P, chain_tail<D, FAM>(F::comb(m, tj3[sj]), sl.tc, j + 1));
+            if (a < 2) {
+              ks_add(S4, x3);  // (+-l4 on i, +-l4 on j)
+              ks_add(S7, F::template outer<D>(
+                             P, chain_tail<D, FAM>(F::comb(m, tj2[sj]), sl.tc, j + 1)));
+            } else {
+              ks_add(S7, x3);  // (+-l2 on i, +-l3 on j)
+            }
+          }
+        }
+      } else {
+        // axis triple i < j < k: class 8
+        int i, j, k;
+        triple_of<D>(it - D - NPAIR, i, j, k);
+        const double ci = sl.c[i], hi = sl.h[i];
+        const double cj = sl.c[j], hj = sl.h[j];
+        const double ck = sl.c[k], hk = sl.h[k];
+        const double ti[2] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci))};
+        const double tj[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
+        const double tk[2] = {F::term(P, k, fma(K.lam4, hk, ck)), F::term(P, k, fma(-K.lam4, hk, ck))};
+        const double pci = sl.pc[i];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const double m1 =
+              chain_mid<FAM>((i == 0) ? ti[a] : F::comb(pci, ti[a]), sl.tc, i + 1, j);
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const double m2 = chain_mid<FAM>(F::comb(m1, tj[b]), sl.tc, j + 1, k);
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+              ks_add(S8, F::template outer<D>(
+                             P, chain_tail<D, FAM>(F::comb(m2, tk[e]), sl.tc, k + 1)));
+          }
+        }
+      }
+    }
+    // Class 5: this lane's 2^(D - LOG2L) corners.
+    {
+      double t5p[D], t5m[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        t5p[j] = F::term(P, j, fma(K.lam5, h[j], c[j]));
+        t5m[j] = F::term(P, j, fma(-K.lam5, h[j], c[j]));
+      }
+      corner_sweep<D, FAM, LOG2L>(P, t5p, t5m, (uint32_t)s, S5);
+    }
+    // Combine the L lanes of the region.
+#pragma unroll
+    for (int m = L / 2; m >= 1; m >>= 1) {
+      S2 = ks_merge(S2, shfl_xor_ks(S2, m));
+      S3 = ks_merge(S3, shfl_xor_ks(S3, m));
+      S4 = ks_merge(S4, shfl_xor_ks(S4, m));
+      S5 = ks_merge(S5, shfl_xor_ks(S5, m));
+      S6 = ks_merge(S6, shfl_xor_ks(S6, m));
+      S7 = ks_merge(S7, shfl_xor_ks(S7, m));
+      S8 = ks_merge(S8, shfl_xor_ks(S8, m));
+    }
+    __syncthreads();
+    if (s == 0 && valid) {
+      const double vol = ldexp(A.vol_omega, -lvl);
+      const double S[8] = {f0,          ks_val(S2), ks_val(S3), ks_val(S4),
+                           ks_val(S5), ks_val(S6), ks_val(S7), ks_val(S8)};
+      RegionResult o;
+      o.nonfinite = 0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) o.nonfinite |= !isfinite(S[q]);
+      double q9 = K.w9[0] * S[0];
+      double n1 = K.e9[0] * S[0];
+#pragma unroll
+      for (int q = 1; q < 8; ++q) {
+        q9 = q9 + K.w9[q] * S[q];
+        n1 = n1 + K.e9[q] * S[q];
+      }
+      n1 = fabs(n1);
+      double q7 = K.w[0] * S[0];
+      double d75 = K.e[0] * S[0];
+#pragma unroll
+      for (int q = 1; q < 5; ++q) {
+        q7 = q7 + K.w[q] * S[q];
+        d75 = d75 + K.e[q] * S[q];
+      }
+      const double n2 = fabs(d75);
+      const double q5 = q7 - d75;
+      const double q3 = K.q3[0] * S[0] + K.q3[1] * S[2];
+      const double n3 = fabs(q5 - q3);
+      o.q = vol * q9;
+      o.err = K.err_model ? vol * (n1 * fmin(1.0, 2.0 * fmax(n1 / n2, n2 / n3))) : vol * n1;
+      double dmax = -1.0, scale = 0.0;
+      for (int i = 0; i < D; ++i) {
+        dmax = sl.dv[i] > dmax ? sl.dv[i] : dmax;
+        scale = sl.sc[i] > scale ? sl.sc[i] : scale;
+      }
+      const double thr = dmax - K.axis_band * scale;
+      int axis = -1;
+      double hb = 0.0, cb = 0.0;
+      for (int i = 0; i < D; ++i) {
+        if (sl.dv[i] >= thr && (axis < 0 || sl.h[i] > hb)) {
+          axis = i;
+          hb = sl.h[i];
+          cb = sl.c[i];
+        }
+      }
+      if (axis < 0) {
+        axis = 0;
+        hb = sl.h[0];
+        cb = sl.c[0];
+      }
+      const double hp = hb * 0.5;
+      o.axis = axis;
+      o.geo = (cb - hp == cb) || (cb + hp == cb) || (hp == 0.0);
+      o.nonfinite |= !F::in_range_rt(P, D, sl.c, sl.h);
+      store_result(A, r, o);
+      dd_add(qs, o.q);
+      dd_add(es, o.err);
+      nonfin |= o.nonfinite;
+    }
+    __syncthreads();
+  }
+  block_partials(A, qs, es, nonfin);
+}
+
+#ifndef GM_RULE_FAMILY
+#error "gm_rule9.hip is compiled once per integrand family (-DGM_RULE_FAMILY=k)"
+#endif
+
+#define GM_R9_CAT2(a, b) a##b
+#define GM_R9_CAT(a, b) GM_R9_CAT2(a, b)
+
+template <int D>
+static RuleKernelFn r9_pick() {
+  return rule9_kernel<D, GM_RULE_FAMILY, rule9_log2l(D)>;
+}
+
+RuleKernelFn GM_R9_CAT(rule9_kernel_f, GM_RULE_FAMILY)(int d) {
+  switch (d) {
+    case 2: return r9_pick<2>();
+    case 3: return r9_pick<3>();
+    case 4: return r9_pick<4>();
+    case 5: return r9_pick<5>();
+    case 6: return r9_pick<6>();
+    case 7: return r9_pick<7>();
+    case 8: return r9_pick<8>();
+    case 9: return r9_pick<9>();
+    case 10: return r9_pick<10>();
+    case 11: return r9_pick<11>();
+    case 12: return r9_pick<12>();
+    case 13: return r9_pick<13>();
+    case 14: return r9_pick<14>();
+    case 15: return r9_pick<15>();
+    case 16: return r9_pick<16>();
+    default: return nullptr;
+  }
+}
+
+}  // namespace gm

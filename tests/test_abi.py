@@ -85,7 +85,8 @@ def test_options_validation():
         gm.set_option("lanes_per_region", 3)
     with pytest.raises(gm.GMError):
         gm.set_option("init_log2_regions", 31)
-    for key, bad in (("rule", 2), ("rule", -1), ("prune", 2), ("timing", 3)):
+    for key, bad in (("rule", 3), ("rule", -1), ("prune", 2), ("timing", 3), ("err_model", 2),
+                     ("err_model", -1)):
         with pytest.raises(gm.GMError):
             gm.set_option(key, bad)
     gm.set_option("max_iters", 10000)
@@ -104,6 +105,22 @@ def test_gauss_kronrod_rule_validates_dimension_before_any_device_work():
         assert ei.value.code == gm.EINVAL
     finally:
         gm.set_option("rule", 0)
+
+
+def test_degree9_rule_refuses_batch_and_gradient_before_any_device_work():
+    gm.set_option("rule", 2)
+    try:
+        with pytest.raises(gm.GMError) as ei:
+            gm.integrate_grad(4, np.ones(6), np.zeros(3), np.ones(3), 1e-6, 1e-16, stream=0)
+        assert ei.value.code == gm.EINVAL
+        with pytest.raises(gm.GMError) as ei:
+            gm.integrate_batch([4], [np.ones(6)], [3], [np.zeros(3)], [np.ones(3)], [1e-6],
+                               [1e-16], 1 << 20, stream=0)
+        assert ei.value.code == gm.EINVAL
+    finally:
+        gm.set_option("rule", 0)
+    gm.set_option("err_model", 1)
+    gm.set_option("err_model", 0)
 
 
 def test_eval_regions_rejects_bad_levels():

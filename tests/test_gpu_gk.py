@@ -103,4 +103,4 @@ def test_gk_rejects_unsupported_calls():
     finally:
         gm.set_option("rule", 0)
     with pytest.raises(gm.GMError):
-        gm.set_option("rule", 2)
+        gm.set_option("rule", 3)
