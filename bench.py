@@ -52,7 +52,8 @@ FLOPS_PER_EVAL = {1: 42.75, 2: 12.75, 3: 17.75, 4: 32.5, 5: 32.75, 6: 32.5, 7: 8
 # from; the figure is reported only while those sources are unchanged.
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "rule_kernel_d8_suite_counters.md")
 RULE_SOURCES = [os.path.join(ROOT, "paper_2511_01573_amd", "csrc", f)
-                for f in ("gm_rule.hip", "gm_family.hpp", "gm_common.hpp", "gm_math.hpp", "gm_api.hip")]
+                for f in ("gm_rule.hip", "gm_corner.hpp", "gm_family.hpp", "gm_common.hpp",
+                          "gm_math.hpp", "gm_api.hip")]
 
 
 def parse():
@@ -68,6 +69,9 @@ def parse():
     ap.add_argument("--grad-tau", type=float, default=1e-6)
     ap.add_argument("--grad-log2cap", type=int, default=27)
     ap.add_argument("--config3-log2cap", type=int, default=27)
+    ap.add_argument("--rule", type=int, default=0, choices=(0, 2),
+                    help="rule of the timed suite: 0 degree 7 (the benchmark), 2 degree 9 "
+                         "(profiling runs; its line carries no FLOP roofline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -251,6 +255,46 @@ def bench_gk(gm, W, closed_forms):
     return out
 
 
+def bench_degree9(gm, W, closed_forms):
+    """The degree-9 rule (both error models) against the degree-7 rule on the
+    d = 8 suite (the 18 integrals of one benchmark step): time to tolerance,
+    integrand evaluations, rule-kernel time and accuracy against the closed
+    form, per case and in total."""
+    cases = W.config2()
+    variants = (("degree7", 0, 0), ("degree9", 2, 0), ("degree9_null_rule", 2, 1))
+    rows = {c["name"]: {"name": c["name"]} for c in cases}
+    totals = {}
+    gm.set_option("timing", 1)
+    try:
+        for key, rule, model in variants:
+            gm.set_option("rule", rule)
+            gm.set_option("err_model", model)
+            run_cases(gm, cases)  # warm-up
+            res = run_cases(gm, cases)
+            worst = 0.0
+            for c, r in zip(cases, res):
+                d = len(c["lo"])
+                ex = float(closed_forms.exact(c["family"], c["params"][:d], c["params"][d:]))
+                rel = abs(r["I"] - ex) / abs(ex)
+                worst = max(worst, rel / c["rel_tol"])
+                rows[c["name"]][key] = {"status": r["status"], "seconds": r["seconds"],
+                                        "evals": r["evals"], "regions": r["regions"],
+                                        "rel_err_vs_closed_form": rel}
+            secs = sum(r["seconds"] for r in res)
+            ev = sum(r["evals"] for r in res)
+            rule_s = sum(r["rule_ms"] for r in res) / 1e3
+            totals[key] = {"seconds": secs, "evals": ev, "regions": sum(r["regions"] for r in res),
+                           "rule_kernel_s": rule_s, "rule_evals_per_s": ev / rule_s,
+                           "status_counts": {str(k): sum(1 for r in res if r["status"] == k)
+                                             for k in sorted({r["status"] for r in res})},
+                           "max_rel_err_over_rel_tol": worst}
+    finally:
+        gm.set_option("timing", 0)
+        gm.set_option("rule", 0)
+        gm.set_option("err_model", 0)
+    return {"totals": totals, "cases": list(rows.values())}
+
+
 def bench_prune(gm, W, closed_forms):
     """Memory-pressure pruning on the suite cases that outgrow their store:
     the oscillatory integral at rel_tol 1e-7 with 2^24 regions, and two d = 8
@@ -327,6 +371,7 @@ def main():
     taus = tuple(float(x) for x in args.taus.split(","))
     cases = W.config2(taus=taus)
     gm.set_option("timing", 1)
+    gm.set_option("rule", args.rule)
     for _ in range(args.warmup):
         run_cases(gm, cases)
     torch.cuda.synchronize()
@@ -337,6 +382,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gm.set_option("timing", 0)
+    gm.set_option("rule", 0)
 
     evals = sum(c["evals"] for st in steps for c in st)
     regions = sum(c["regions"] for st in steps for c in st)
@@ -345,10 +391,11 @@ def main():
     rule_s = sum(c["rule_ms"] for st in steps for c in st) / 1e3
     flops = sum(c["evals"] * FLOPS_PER_EVAL[c["family"]] for st in steps for c in st)
     launches = sum(c["rule_launches"] for st in steps for c in st)
-    achieved = flops / rule_s / 1e12
+    achieved = flops / rule_s / 1e12 if args.rule == 0 else None
     last = steps[-1]
     out = {
-        "metric": "integrand evals/s (d=8 six-family Genz suite, rel_tol 1e-3/1e-5/1e-7)",
+        "metric": "integrand evals/s (d=8 six-family Genz suite, rel_tol 1e-3/1e-5/1e-7)"
+                  + (" with the degree-9 rule" if args.rule else ""),
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -365,7 +412,9 @@ def main():
         "regions_per_s": regions / wall,
         "roofline": {"bound": "alu", "kernel": "rule (FP64 vector)", "achieved": achieved,
                      "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS if achieved else None,
+                     "traffic": measured_traffic() if args.rule == 0 else None,
+                     "traffic_unit": "HBM bytes per launch",
                      "rule_kernel_s": rule_s, "rule_launches": launches,
                      "rule_avg_launch_ms": rule_s / launches * 1e3,
                      "rule_evals_per_s": evals / rule_s},
@@ -380,6 +429,7 @@ def main():
         out["config3"] = bench_config3(gm, W, closed_forms, args.config3_log2cap)
         out["gauss_kronrod"] = bench_gk(gm, W, closed_forms)
         out["prune"] = bench_prune(gm, W, closed_forms)
+        out["degree9"] = bench_degree9(gm, W, closed_forms)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

@@ -57,11 +57,15 @@ __device__ __forceinline__ void triple_of(int p, int& i, int& j, int& k) {
   k = j + 1 + p;
 }
 
-// Chain of centre terms over coordinates k0 .. k1-1 below s.
-template <int FAM>
-__device__ __forceinline__ double chain_mid(double s, const double* tc, int k0, int k1) {
-  for (int k = k0; k < k1; ++k) s = Fam<FAM>::comb(s, tc[k]);
-  return s;
+// Extend N node arguments by the centre terms of coordinates k0 .. k1-1, in
+// order (one loop for all N chains: each step is one LDS read and N (+)).
+template <int FAM, int N>
+__device__ __forceinline__ void chain_n(double (&x)[N], const double* tc, int k0, int k1) {
+  for (int k = k0; k < k1; ++k) {
+    const double t = tc[k];
+#pragma unroll
+    for (int q = 0; q < N; ++q) x[q] = Fam<FAM>::comb(x[q], t);
+  }
 }
 
 template <int D, int FAM, int LOG2L>
@@ -71,7 +75,6 @@ __global__ __launch_bounds__(kRuleBlock) void rule9_kernel(RuleArgs A) {
   constexpr int RPB = kRuleBlock / L;  // regions per block step
   constexpr int NPAIR = D * (D - 1) / 2;
   constexpr int NTRI = D * (D - 1) * (D - 2) / 6;
-  constexpr int NITEM = D + NPAIR + NTRI;
   static_assert(LOG2L <= D && LOG2L <= 6, "at least one corner and one wavefront per region");
   __shared__ R9Slot<D> slots[RPB];
   int64_t start, n;
@@ -123,86 +126,95 @@ __global__ __launch_bounds__(kRuleBlock) void rule9_kernel(RuleArgs A) {
     const double f0 = F::template outer<D>(P, pc);
     KSum S2 = {0.0, 0.0}, S3 = {0.0, 0.0}, S4 = {0.0, 0.0}, S5 = {0.0, 0.0};
     KSum S6 = {0.0, 0.0}, S7 = {0.0, 0.0}, S8 = {0.0, 0.0};
-    for (int it = s; it < NITEM; it += L) {
-      if (it < D) {
-        // axis i: +-l2, +-l3, +-l6 and the fourth difference
-        const int i = it;
-        const double ci = sl.c[i], hi = sl.h[i];
-        const double v[6] = {F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci)),
-                             F::term(P, i, fma(K.lam3, hi, ci)), F::term(P, i, fma(-K.lam3, hi, ci)),
-                             F::term(P, i, fma(K.lam6, hi, ci)), F::term(P, i, fma(-K.lam6, hi, ci))};
-        const double pci = sl.pc[i];
-        double f[6];
+    // The three node groups run one after the other, so the lanes of a
+    // wavefront stay on the same code path.
+    // Axes: +-l2, +-l3, +-l6 along axis i and its fourth difference.
+    for (int i = s; i < D; i += L) {
+      const double ci = sl.c[i], hi = sl.h[i];
+      const double v[6] = {F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci)),
+                           F::term(P, i, fma(K.lam3, hi, ci)), F::term(P, i, fma(-K.lam3, hi, ci)),
+                           F::term(P, i, fma(K.lam6, hi, ci)), F::term(P, i, fma(-K.lam6, hi, ci))};
+      const double pci = sl.pc[i];
+      double x[6], f[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          const double s0 = (i == 0) ? v[q] : F::comb(pci, v[q]);
-          f[q] = F::template outer<D>(P, chain_tail<D, FAM>(s0, sl.tc, i + 1));
-        }
-        ks_add(S2, f[0]);
-        ks_add(S2, f[1]);
-        ks_add(S3, f[2]);
-        ks_add(S3, f[3]);
-        ks_add(S6, f[4]);
-        ks_add(S6, f[5]);
-        double dv, scv;
-        fourth_diff(K, f0, f[0], f[1], f[2], f[3], dv, scv);
-        sl.dv[i] = dv;
-        sl.sc[i] = scv;
-      } else if (it < D + NPAIR) {
-        // axis pair i < j: class 4 (+-l4, +-l4) and class 7 in both orders
-        int i, j;
-        pair_of<D>(it - D, i, j);
-        const double ci = sl.c[i], hi = sl.h[i], cj = sl.c[j], hj = sl.h[j];
-        // x_i at +l3, -l3 (= +-l4), +l2, -l2
-        const double ti[4] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci)),
-                              F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci))};
-        const double tj3[2] = {F::term(P, j, fma(K.lam4, hj, cj)),
-                               F::term(P, j, fma(-K.lam4, hj, cj))};
-        const double tj2[2] = {F::term(P, j, fma(K.lam2, hj, cj)),
-                               F::term(P, j, fma(-K.lam2, hj, cj))};
-        const double pci = sl.pc[i];
+      for (int q = 0; q < 6; ++q) x[q] = (i == 0) ? v[q] : F::comb(pci, v[q]);
+      chain_n<FAM, 6>(x, sl.tc, i + 1, D);
+      F::template outer_n<D, 6>(P, x, f);
+      ks_add(S2, f[0]);
+      ks_add(S2, f[1]);
+      ks_add(S3, f[2]);
+      ks_add(S3, f[3]);
+      ks_add(S6, f[4]);
+      ks_add(S6, f[5]);
+      double dv, scv;
+      fourth_diff(K, f0, f[0], f[1], f[2], f[3], dv, scv);
+      sl.dv[i] = dv;
+      sl.sc[i] = scv;
+    }
+    // Axis pairs i < j: class 4 (+-l4, +-l4) and class 7 in both orders.
+    for (int it = s; it < NPAIR; it += L) {
+      int i, j;
+      pair_of<D>(it, i, j);
+      const double ci = sl.c[i], hi = sl.h[i], cj = sl.c[j], hj = sl.h[j];
+      // x_i at +l3, -l3 (= +-l4), +l2, -l2
+      const double ti[4] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci)),
+                            F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci))};
+      const double tj3[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
+      const double tj2[2] = {F::term(P, j, fma(K.lam2, hj, cj)), F::term(P, j, fma(-K.lam2, hj, cj))};
+      const double pci = sl.pc[i];
+      double m[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const double m =
-              chain_mid<FAM>((i == 0) ? ti[a] : F::comb(pci, ti[a]), sl.tc, i + 1, j);
+      for (int a = 0; a < 4; ++a) m[a] = (i == 0) ? ti[a] : F::comb(pci, ti[a]);
+      chain_n<FAM, 4>(m, sl.tc, i + 1, j);
+      // x[0..4): (+-l4 on i, +-l4 on j), class 4; x[4..12): (+-l3 on i, +-l2 on
+      // j) and (+-l2 on i, +-l3 on j), class 7
+      double x[12], f[12];
 #pragma unroll
-          for (int sj = 0; sj < 2; ++sj) {
-            const double x3 =
-                F::template outer<D>(P, chain_tail<D, FAM>(F::comb(m, tj3[sj]), sl.tc, j + 1));
-            if (a < 2) {
-              ks_add(S4, x3);  // (+-l4 on i, +-l4 on j)
-              ks_add(S7, F::template outer<D>(
-                             P, chain_tail<D, FAM>(F::comb(m, tj2[sj]), sl.tc, j + 1)));
-            } else {
-              ks_add(S7, x3);  // (+-l2 on i, +-l3 on j)
-            }
-          }
-        }
-      } else {
-        // axis triple i < j < k: class 8
-        int i, j, k;
-        triple_of<D>(it - D - NPAIR, i, j, k);
-        const double ci = sl.c[i], hi = sl.h[i];
-        const double cj = sl.c[j], hj = sl.h[j];
-        const double ck = sl.c[k], hk = sl.h[k];
-        const double ti[2] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci))};
-        const double tj[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
-        const double tk[2] = {F::term(P, k, fma(K.lam4, hk, ck)), F::term(P, k, fma(-K.lam4, hk, ck))};
-        const double pci = sl.pc[i];
+      for (int a = 0; a < 2; ++a) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const double m1 =
-              chain_mid<FAM>((i == 0) ? ti[a] : F::comb(pci, ti[a]), sl.tc, i + 1, j);
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            const double m2 = chain_mid<FAM>(F::comb(m1, tj[b]), sl.tc, j + 1, k);
-#pragma unroll
-            for (int e = 0; e < 2; ++e)
-              ks_add(S8, F::template outer<D>(
-                             P, chain_tail<D, FAM>(F::comb(m2, tk[e]), sl.tc, k + 1)));
-          }
+        for (int sj = 0; sj < 2; ++sj) {
+          x[2 * a + sj] = F::comb(m[a], tj3[sj]);
+          x[4 + 2 * a + sj] = F::comb(m[a], tj2[sj]);
+          x[8 + 2 * a + sj] = F::comb(m[2 + a], tj3[sj]);
         }
       }
+      chain_n<FAM, 12>(x, sl.tc, j + 1, D);
+      F::template outer_n<D, 12>(P, x, f);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ks_add(S4, f[q]);
+#pragma unroll
+      for (int q = 4; q < 12; ++q) ks_add(S7, f[q]);
+    }
+    // Axis triples i < j < k: class 8.
+    for (int it = s; it < NTRI; it += L) {
+      int i, j, k;
+      triple_of<D>(it, i, j, k);
+      const double ci = sl.c[i], hi = sl.h[i];
+      const double cj = sl.c[j], hj = sl.h[j];
+      const double ck = sl.c[k], hk = sl.h[k];
+      const double ti[2] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci))};
+      const double tj[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
+      const double tk[2] = {F::term(P, k, fma(K.lam4, hk, ck)), F::term(P, k, fma(-K.lam4, hk, ck))};
+      const double pci = sl.pc[i];
+      double m1[2], m2[4], x8[8], f8[8];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) m1[a] = (i == 0) ? ti[a] : F::comb(pci, ti[a]);
+      chain_n<FAM, 2>(m1, sl.tc, i + 1, j);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) m2[2 * a + b] = F::comb(m1[a], tj[b]);
+      }
+      chain_n<FAM, 4>(m2, sl.tc, j + 1, k);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) x8[2 * q + e] = F::comb(m2[q], tk[e]);
+      }
+      chain_n<FAM, 8>(x8, sl.tc, k + 1, D);
+      F::template outer_n<D, 8>(P, x8, f8);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) ks_add(S8, f8[q]);
     }
     // Class 5: this lane's 2^(D - LOG2L) corners.
     {
