@@ -37,25 +37,30 @@ struct R9Slot {
   double c[D], h[D], tc[D], pc[D], dv[D], sc[D];
 };
 
-// The (i, j, k) triple with lexicographic index p, i < j < k < D.
+// Work-item tables: the axis pairs (i, j) and triples (i, j, k), packed 4
+// bits per index, ordered by their last index so that the lanes of a round
+// run tail chains of about the same length.
 template <int D>
-__device__ __forceinline__ void triple_of(int p, int& i, int& j, int& k) {
-  i = 0;
-  int cnt = (D - 1) * (D - 2) / 2;  // triples whose first index is i
-  while (p >= cnt) {
-    p -= cnt;
-    ++i;
-    cnt = (D - 1 - i) * (D - 2 - i) / 2;
-  }
-  j = i + 1;
-  int row = D - 1 - j;  // triples (i, j, k) with this j
-  while (p >= row) {
-    p -= row;
-    ++j;
-    --row;
-  }
-  k = j + 1 + p;
+struct ItemTable {
+  uint16_t pair[D * (D - 1) / 2 + 1];
+  uint16_t tri[D * (D - 1) * (D - 2) / 6 + 1];
+};
+
+template <int D>
+constexpr ItemTable<D> make_items() {
+  ItemTable<D> t{};
+  int n = 0;
+  for (int j = 1; j < D; ++j)
+    for (int i = 0; i < j; ++i) t.pair[n++] = (uint16_t)(i | (j << 4));
+  n = 0;
+  for (int k = 2; k < D; ++k)
+    for (int j = 1; j < k; ++j)
+      for (int i = 0; i < j; ++i) t.tri[n++] = (uint16_t)(i | (j << 4) | (k << 8));
+  return t;
 }
+
+template <int D>
+__device__ constexpr ItemTable<D> kItems = make_items<D>();
 
 // Extend N node arguments by the centre terms of coordinates k0 .. k1-1, in
 // order (one loop for all N chains: each step is one LDS read and N (+)).
@@ -68,8 +73,11 @@ __device__ __forceinline__ void chain_n(double (&x)[N], const double* tc, int k0
   }
 }
 
+// Three wavefronts per SIMD up to d = 10 (a few values spill to scratch, and
+// the extra wavefront hides more latency); two above, where the spill grows.
 template <int D, int FAM, int LOG2L>
-__global__ __launch_bounds__(kRuleBlock) void rule9_kernel(RuleArgs A) {
+__global__ __launch_bounds__(kRuleBlock) __attribute__((amdgpu_waves_per_eu(D <= 10 ? 3 : 2)))
+void rule9_kernel(RuleArgs A) {
   using F = Fam<FAM>;
   constexpr int L = 1 << LOG2L;
   constexpr int RPB = kRuleBlock / L;  // regions per block step
@@ -153,8 +161,8 @@ __global__ __launch_bounds__(kRuleBlock) void rule9_kernel(RuleArgs A) {
     }
     // Axis pairs i < j: class 4 (+-l4, +-l4) and class 7 in both orders.
     for (int it = s; it < NPAIR; it += L) {
-      int i, j;
-      pair_of<D>(it, i, j);
+      const int pk = kItems<D>.pair[it];
+      const int i = pk & 15, j = pk >> 4;
       const double ci = sl.c[i], hi = sl.h[i], cj = sl.c[j], hj = sl.h[j];
       // x_i at +l3, -l3 (= +-l4), +l2, -l2
       const double ti[4] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci)),
@@ -187,8 +195,8 @@ __global__ __launch_bounds__(kRuleBlock) void rule9_kernel(RuleArgs A) {
     }
     // Axis triples i < j < k: class 8.
     for (int it = s; it < NTRI; it += L) {
-      int i, j, k;
-      triple_of<D>(it, i, j, k);
+      const int tk3 = kItems<D>.tri[it];
+      const int i = tk3 & 15, j = (tk3 >> 4) & 15, k = tk3 >> 8;
       const double ci = sl.c[i], hi = sl.h[i];
       const double cj = sl.c[j], hj = sl.h[j];
       const double ck = sl.c[k], hk = sl.h[k];
