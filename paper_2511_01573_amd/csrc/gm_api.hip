@@ -903,7 +903,8 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   }
 
   // Iterations launched back to back before the host reads the status
-  // block: kernels take the active count from the device and return at once
+  // block (6 while the active set is below 2^16 regions, 3 below 2^20, 2
+  // above): kernels take the active count from the device and return at once
   // after a final status, so launches past the end cost only their launch.
   // Grids are sized for the largest count the iteration can have (n doubles
   // at most per iteration).  Gradient mode checks every iteration (the leaf
@@ -922,7 +923,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   for (;;) {
     int K = 1;
     if (!keep_leaves)
-      K = g_opt.graph_iters > 0 ? std::min(g_opt.graph_iters, kMaxAhead) : (n < (1 << 18) ? 4 : 1);
+      K = g_opt.graph_iters > 0 ? std::min(g_opt.graph_iters, kMaxAhead) : (n < (1 << 16) ? 6 : n < (1 << 20) ? 3 : 2);
     if (keep_leaves) {
       // Room for every region of this iteration to retire.
       rc = leaf_reserve(d, leaves_have + n, leaves_have, s);

@@ -25,9 +25,10 @@
 // 2^(d - log2 L) corners as a binary tree; the O(d^3) nodes of the other
 // classes are dealt out as work items (an axis: its 6 nodes and its fourth
 // difference; an axis pair: 4 class-4 and 8 class-7 nodes; an axis triple: 8
-// class-8 nodes).  Every node argument is the left-to-right chain of the
-// per-coordinate terms, as in the degree-7 kernel, so node values match the
-// defining formula's evaluation order bitwise.
+// class-8 nodes).  An item's nodes of one class are summed plainly and the
+// sum enters the class's compensated total.  Every node argument is the
+// left-to-right chain of the per-coordinate terms, as in the degree-7 kernel,
+// so node values match the defining formula's evaluation order bitwise.
 #include "gm_corner.hpp"
 
 namespace gm {
@@ -148,12 +149,9 @@ void rule9_kernel(RuleArgs A) {
       for (int q = 0; q < 6; ++q) x[q] = (i == 0) ? v[q] : F::comb(pci, v[q]);
       chain_n<FAM, 6>(x, sl.tc, i + 1, D);
       F::template outer_n<D, 6>(P, x, f);
-      ks_add(S2, f[0]);
-      ks_add(S2, f[1]);
-      ks_add(S3, f[2]);
-      ks_add(S3, f[3]);
-      ks_add(S6, f[4]);
-      ks_add(S6, f[5]);
+      ks_add(S2, f[0] + f[1]);
+      ks_add(S3, f[2] + f[3]);
+      ks_add(S6, f[4] + f[5]);
       double dv, scv;
       fourth_diff(K, f0, f[0], f[1], f[2], f[3], dv, scv);
       sl.dv[i] = dv;
@@ -188,10 +186,8 @@ void rule9_kernel(RuleArgs A) {
       }
       chain_n<FAM, 12>(x, sl.tc, j + 1, D);
       F::template outer_n<D, 12>(P, x, f);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) ks_add(S4, f[q]);
-#pragma unroll
-      for (int q = 4; q < 12; ++q) ks_add(S7, f[q]);
+      ks_add(S4, (f[0] + f[1]) + (f[2] + f[3]));
+      ks_add(S7, ((f[4] + f[5]) + (f[6] + f[7])) + ((f[8] + f[9]) + (f[10] + f[11])));
     }
     // Axis triples i < j < k: class 8.
     for (int it = s; it < NTRI; it += L) {
@@ -221,8 +217,7 @@ void rule9_kernel(RuleArgs A) {
       }
       chain_n<FAM, 8>(x8, sl.tc, k + 1, D);
       F::template outer_n<D, 8>(P, x8, f8);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) ks_add(S8, f8[q]);
+      ks_add(S8, ((f8[0] + f8[1]) + (f8[2] + f8[3])) + ((f8[4] + f8[5]) + (f8[6] + f8[7])));
     }
     // Class 5: this lane's 2^(D - LOG2L) corners.
     {
