@@ -255,11 +255,11 @@ def bench_gk(gm, W, closed_forms):
     return out
 
 
-def bench_degree9(gm, W, closed_forms):
+def bench_degree9(gm, W, closed_forms, log2cap: int):
     """The degree-9 rule (both error models) against the degree-7 rule on the
     d = 8 suite (the 18 integrals of one benchmark step): time to tolerance,
     integrand evaluations, rule-kernel time and accuracy against the closed
-    form, per case and in total."""
+    form, per case and in total; then the d = 12 / 16 cases with degree 9."""
     cases = W.config2()
     variants = (("degree7", 0, 0), ("degree9", 2, 0), ("degree9_null_rule", 2, 1))
     rows = {c["name"]: {"name": c["name"]} for c in cases}
@@ -288,11 +288,28 @@ def bench_degree9(gm, W, closed_forms):
                            "status_counts": {str(k): sum(1 for r in res if r["status"] == k)
                                              for k in sorted({r["status"] for r in res})},
                            "max_rel_err_over_rel_tol": worst}
+        # the d = 12 / 16 cases with the degree-9 rule (the degree-7 runs are
+        # the "config3" section)
+        gm.set_option("rule", 2)
+        gm.set_option("err_model", 0)
+        high = []
+        for c in W.config3(max_regions=1 << log2cap):
+            d = len(c["lo"])
+            t0 = time.perf_counter()
+            I, E, st = gm.integrate(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"],
+                                    c["abs_tol"], c["max_regions"])
+            dt = time.perf_counter() - t0
+            s = gm.last_stats()
+            ex = float(closed_forms.exact(c["family"], c["params"][:d], c["params"][d:]))
+            high.append({"name": c["name"], "status": st, "seconds": dt, "evals": s["evals"],
+                         "regions": s["regions_evaluated"],
+                         "rule_evals_per_s": s["evals"] / max(s["rule_ms"] * 1e-3, 1e-12),
+                         "rel_err_vs_closed_form": abs(I - ex) / abs(ex)})
     finally:
         gm.set_option("timing", 0)
         gm.set_option("rule", 0)
         gm.set_option("err_model", 0)
-    return {"totals": totals, "cases": list(rows.values())}
+    return {"totals": totals, "cases": list(rows.values()), "config3": high}
 
 
 def bench_prune(gm, W, closed_forms):
@@ -429,7 +446,7 @@ def main():
         out["config3"] = bench_config3(gm, W, closed_forms, args.config3_log2cap)
         out["gauss_kronrod"] = bench_gk(gm, W, closed_forms)
         out["prune"] = bench_prune(gm, W, closed_forms)
-        out["degree9"] = bench_degree9(gm, W, closed_forms)
+        out["degree9"] = bench_degree9(gm, W, closed_forms, args.config3_log2cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))
