@@ -181,11 +181,34 @@ def bench_batch(gm, W, closed_forms):
                                             b["his"][i], b["rel_tols"][i], b["abs_tols"][i], 1 << 26)
     ts = time.perf_counter() - t0
     agree = float(np.max(np.abs(single - est) / np.maximum(np.abs(est), 1e-300)))
-    relerr = []
-    for i in range(0, n, 16):
-        d = b["ds"][i]
-        ex = float(closed_forms.exact(b["families"][i], b["params"][i][:d], b["params"][i][d:]))
-        relerr.append(abs(est[i] - ex) / abs(ex))
+
+    def every16(values):
+        out = []
+        for i in range(0, n, 16):
+            d = b["ds"][i]
+            ex = float(closed_forms.exact(b["families"][i], b["params"][i][:d],
+                                          b["params"][i][d:]))
+            out.append(abs(values[i] - ex) / abs(ex))
+        return max(out)
+
+    relerr = [every16(est)]
+    # the same batch with the degree-9 rule
+    gm.set_option("graph_iters", 8)
+    gm.set_option("rule", 2)
+    try:
+        gm.integrate_batch(*args, cap)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc9, est9, err9, st9 = gm.integrate_batch(*args, cap)
+        t9 = time.perf_counter() - t0
+        s9 = gm.last_stats()
+    finally:
+        gm.set_option("graph_iters", 0)
+        gm.set_option("rule", 0)
+    deg9 = {"batch_s": t9, "batch_integrals_per_s": n / t9, "batch_evals": s9["evals"],
+            "speedup_vs_degree7_batch": tb / t9, "speedup_vs_degree7_singles": ts / t9,
+            "status_counts": {str(k): int((st9 == k).sum()) for k in set(st9.tolist())},
+            "max_rel_err_vs_closed_form_every_16th": every16(est9)}
     return {"integrals": n, "batch_s": tb, "batch_integrals_per_s": n / tb,
             "batch_evals": bstats["evals"], "batch_evals_per_s": bstats["evals"] / tb,
             "single_s": ts, "single_integrals_per_s": n / ts, "speedup": ts / tb,
@@ -194,7 +217,7 @@ def bench_batch(gm, W, closed_forms):
             "max_rel_diff_batch_vs_single": agree,
             "max_rel_err_vs_closed_form_every_16th": max(relerr),
             "difficulty_scale": W.BATCH_SCALE,
-            "tile_table": "autotuned" if table else "default"}
+            "tile_table": "autotuned" if table else "default", "degree9": deg9}
 
 
 def bench_config3(gm, W, closed_forms, log2cap: int):

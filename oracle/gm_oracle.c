@@ -1373,6 +1373,16 @@ int gmo_integrate_batch(int n, const int* fam, const double* params, const int* 
                         const double* abs_tol, int64_t max_regions_total, int init_log2,
                         int max_iters, double* out_est, double* out_err, int* out_status,
                         int64_t* out_iters) {
+  return gmo_integrate_batch_rule(n, fam, params, d, lo, hi, rel_tol, abs_tol, max_regions_total,
+                                  init_log2, max_iters, 0, 0, out_est, out_err, out_status,
+                                  out_iters);
+}
+
+int gmo_integrate_batch_rule(int n, const int* fam, const double* params, const int* d,
+                             const double* lo, const double* hi, const double* rel_tol,
+                             const double* abs_tol, int64_t max_regions_total, int init_log2,
+                             int max_iters, int rule, int err_model, double* out_est,
+                             double* out_err, int* out_status, int64_t* out_iters) {
   gmo_run** runs;
   int i, worst = 0, running;
   int64_t po = 0, bo = 0;
@@ -1385,7 +1395,14 @@ int gmo_integrate_batch(int n, const int* fam, const double* params, const int* 
                          max_regions_total, init_log2, max_iters, 0, &st);
     po += 2 * d[i];
     bo += d[i];
-    if (!runs[i]) out_status[i] = st;
+    if (!runs[i]) {
+      out_status[i] = st;
+    } else if (gmo_set_rule(runs[i], rule) != GMO_OK ||
+               gmo_set_err_model(runs[i], err_model) != GMO_OK) {
+      gmo_free(runs[i]);
+      runs[i] = NULL;
+      out_status[i] = GMO_EINVAL;
+    }
   }
   /* The initial partitions must fit together. */
   {

@@ -164,6 +164,14 @@ int gmo_integrate_batch(int n, const int* fam, const double* params, const int* 
                         const double* abs_tol, int64_t max_regions_total, int init_log2,
                         int max_iters, double* out_est, double* out_err, int* out_status,
                         int64_t* out_iters);
+/* The same with the rule and error model of every item selected (rule as in
+   gmo_set_rule, err_model as in gmo_set_err_model; an item that rejects them
+   reports GMO_EINVAL). */
+int gmo_integrate_batch_rule(int n, const int* fam, const double* params, const int* d,
+                             const double* lo, const double* hi, const double* rel_tol,
+                             const double* abs_tol, int64_t max_regions_total, int init_log2,
+                             int max_iters, int rule, int err_model, double* out_est,
+                             double* out_err, int* out_status, int64_t* out_iters);
 
 #ifdef __cplusplus
 }

@@ -111,6 +111,10 @@ def lib():
         L.gmo_set_prune.argtypes = [C.c_void_p, C.c_int]
         L.gmo_pruned.restype = C.c_int
         L.gmo_pruned.argtypes = [C.c_void_p]
+        L.gmo_integrate_batch_rule.restype = C.c_int
+        L.gmo_integrate_batch_rule.argtypes = [C.c_int, ip, dp, ip, dp, dp, dp, dp, C.c_int64,
+                                               C.c_int, C.c_int, C.c_int, C.c_int, dp, dp, ip,
+                                               i64p]
         L.gmo_integrate_batch.restype = C.c_int
         L.gmo_integrate_batch.argtypes = [C.c_int, ip, dp, ip, dp, dp, dp, dp, C.c_int64, C.c_int,
                                           C.c_int, dp, dp, ip, i64p]
@@ -401,7 +405,7 @@ def integrate_grad(fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 <<
 
 
 def integrate_batch(fams, params_list, ds, los, his, rel_tols, abs_tols, max_regions_total,
-                    init_log2=12, max_iters=10000):
+                    init_log2=12, max_iters=10000, rule_id=0, err_model=0):
     n = len(fams)
     fam = np.ascontiguousarray(fams, dtype=np.intc)
     d = np.ascontiguousarray(ds, dtype=np.intc)
@@ -416,10 +420,12 @@ def integrate_batch(fams, params_list, ds, los, his, rel_tols, abs_tols, max_reg
     its = np.zeros(n, dtype=np.int64)
     P = C.POINTER(C.c_double)
     IP = C.POINTER(C.c_int)
-    rc = lib().gmo_integrate_batch(n, fam.ctypes.data_as(IP), params.ctypes.data_as(P),
-                                   d.ctypes.data_as(IP), lo.ctypes.data_as(P),
-                                   hi.ctypes.data_as(P), rt.ctypes.data_as(P),
-                                   at.ctypes.data_as(P), int(max_regions_total), int(init_log2),
-                                   int(max_iters), est.ctypes.data_as(P), err.ctypes.data_as(P),
-                                   st.ctypes.data_as(IP), its.ctypes.data_as(C.POINTER(C.c_int64)))
+    rc = lib().gmo_integrate_batch_rule(n, fam.ctypes.data_as(IP), params.ctypes.data_as(P),
+                                        d.ctypes.data_as(IP), lo.ctypes.data_as(P),
+                                        hi.ctypes.data_as(P), rt.ctypes.data_as(P),
+                                        at.ctypes.data_as(P), int(max_regions_total),
+                                        int(init_log2), int(max_iters), int(rule_id),
+                                        int(err_model), est.ctypes.data_as(P),
+                                        err.ctypes.data_as(P), st.ctypes.data_as(IP),
+                                        its.ctypes.data_as(C.POINTER(C.c_int64)))
     return rc, est, err, st, its

@@ -14,7 +14,8 @@
 //
 // One iteration (a fixed launch sequence, replayed from a hipGraph):
 //   rule      one launch per (d, family) group, the group range read on the
-//             device (tile shape per group from the tuning table)
+//             device (tile shape per group from the tuning table; the
+//             degree-9 rule, option rule = 2, uses its own lane mapping)
 //   reduce    one workgroup per chunk: double-double sums of Q and err
 //   finalize  one wavefront per item: I, E over its chunks, T, stopping rule
 //   classify  one workgroup per chunk: retire test, in-chunk ballot ranks,
@@ -41,7 +42,6 @@
 
 namespace gm {
 
-constexpr int kBatchMaxDim = kTprMaxDim;  // batch items have 2 <= d <= 10
 constexpr int kChunk = 1024;              // regions per chunk = threads per chunk workgroup
 constexpr int kChunkGrid = 2048;          // grid-stride workgroups of the chunk kernels
 constexpr int kMaxBatchItems = 65536;     // item slots the workspace is sized for
@@ -604,7 +604,7 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
               double* out_est, double* out_err, int* out_status, hipStream_t s) {
   const auto t_start = std::chrono::steady_clock::now();
   const Options& opt = options();
-  if (opt.rule != 0) return GM_EINVAL;  // batch items use the Genz-Malik rule
+  if (opt.rule == 1) return GM_EINVAL;  // the Gauss-Kronrod rule is for single integrals
   if (opt.prune != 0) return GM_EINVAL;  // the batch's shared capacity has its own rule
   // Per-item offsets into the packed inputs and validation.
   std::vector<int64_t> poff(n), boff(n);
@@ -777,9 +777,15 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
     ra.VOL = (const double*)(base + lay.vol);
     ra.grp = A.group_range + 2 * g;
     ra.bbuf = &A.bst->buf;
-    const Tile t = tile_for(gd[g], gfam[g]);
-    rfn[g] = rule_kernel(gd[g], gfam[g], t.log2l, true);
-    rgrid[g] = t.grid > 0 ? t.grid : 2048;
+    if (opt.rule == 2) {
+      // degree 9: the kernel's own lane mapping, a fixed grid-stride grid
+      rfn[g] = r9_kernel(gd[g], gfam[g], true);
+      rgrid[g] = 2048;
+    } else {
+      const Tile t = tile_for(gd[g], gfam[g]);
+      rfn[g] = rule_kernel(gd[g], gfam[g], t.log2l, true);
+      rgrid[g] = t.grid > 0 ? t.grid : 2048;
+    }
     if (!rfn[g]) return GM_EINVAL;
   }
   const int item_grid = (nv * 64 + 255) / 256;
@@ -897,7 +903,7 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
     out_status[i] = items[k].status;
     worst = std::max(worst, (int)items[k].status);
     regions += items[k].regions;
-    evals += items[k].regions * gm_num_nodes(items[k].d);
+    evals += items[k].regions * nodes_per_region(items[k].d);
   }
   gm_stats& st = stats_ref();
   st.iterations = hb.iter;

@@ -233,6 +233,7 @@ RuleKernelFn rule_kernel_f5(int d, int log2l, bool batch);
 RuleKernelFn rule_kernel_f6(int d, int log2l, bool batch);
 RuleKernelFn rule_kernel_f7(int d, int log2l, bool batch);
 constexpr int kTprMaxDim = 10;
+constexpr int kBatchMaxDim = kTprMaxDim;  // batch items have 2 <= d <= 10
 constexpr int kRuleBlockSize = 256;
 
 // Tensor-product Gauss-Kronrod rule kernels (one wavefront per region), one
@@ -246,16 +247,16 @@ RuleKernelFn gk_kernel_f6(int d);
 RuleKernelFn gk_kernel_f7(int d);
 constexpr int kGkMaxDim = 6;
 
-// Degree-9 fully symmetric rule kernels, one launcher per family, 2 <= d <= 16;
-// 2^rule9_log2l(d) lanes of one wavefront per region (at least one corner and
-// at most 64 lanes per region).
-RuleKernelFn rule9_kernel_f1(int d);
-RuleKernelFn rule9_kernel_f2(int d);
-RuleKernelFn rule9_kernel_f3(int d);
-RuleKernelFn rule9_kernel_f4(int d);
-RuleKernelFn rule9_kernel_f5(int d);
-RuleKernelFn rule9_kernel_f6(int d);
-RuleKernelFn rule9_kernel_f7(int d);
+// Degree-9 fully symmetric rule kernels, one launcher per family, 2 <= d <= 16
+// (batch-store kernels: d <= kBatchMaxDim); 2^rule9_log2l(d) lanes of one
+// wavefront per region (at least one corner and at most 64 lanes per region).
+RuleKernelFn rule9_kernel_f1(int d, bool batch);
+RuleKernelFn rule9_kernel_f2(int d, bool batch);
+RuleKernelFn rule9_kernel_f3(int d, bool batch);
+RuleKernelFn rule9_kernel_f4(int d, bool batch);
+RuleKernelFn rule9_kernel_f5(int d, bool batch);
+RuleKernelFn rule9_kernel_f6(int d, bool batch);
+RuleKernelFn rule9_kernel_f7(int d, bool batch);
 constexpr int rule9_log2l(int d) { return d - 4 < 2 ? 2 : (d - 4 > 6 ? 6 : d - 4); }
 
 }  // namespace gm

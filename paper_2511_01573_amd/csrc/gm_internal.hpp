@@ -62,6 +62,10 @@ hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, h
 // else log2 of the lanes per region.
 int choose_mapping(int d, int64_t n);
 RuleKernelFn rule_kernel(int d, int fam, int log2l, bool batch);
+// Degree-9 rule kernel of (d, family): single-store or batch-store variant.
+RuleKernelFn r9_kernel(int d, int fam, bool batch);
+// Nodes of the rule the options select.
+int64_t nodes_per_region(int d);
 bool mapping_allowed(int d, int log2l);
 int rule_grid(int log2l, int64_t n);
 int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,

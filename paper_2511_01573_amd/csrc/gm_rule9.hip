@@ -76,7 +76,7 @@ __device__ __forceinline__ void chain_n(double (&x)[N], const double* tc, int k0
 
 // Three wavefronts per SIMD up to d = 10 (a few values spill to scratch, and
 // the extra wavefront hides more latency); two above, where the spill grows.
-template <int D, int FAM, int LOG2L>
+template <int D, int FAM, int LOG2L, bool BATCH>
 __global__ __launch_bounds__(kRuleBlock) __attribute__((amdgpu_waves_per_eu(D <= 10 ? 3 : 2)))
 void rule9_kernel(RuleArgs A) {
   using F = Fam<FAM>;
@@ -88,10 +88,9 @@ void rule9_kernel(RuleArgs A) {
   __shared__ R9Slot<D> slots[RPB];
   int64_t start, n;
   int buf;
-  if (!active_range<false>(A, start, n, buf)) return;
-  const RegionSrc R = region_src<false>(A, buf);
+  if (!active_range<BATCH>(A, start, n, buf)) return;
+  const RegionSrc R = region_src<BATCH>(A, buf);
   const RuleConsts& K = A.K;
-  const DevParams& P = A.P;
   const int g = threadIdx.x >> LOG2L;  // region slot in the block
   const int s = threadIdx.x & (L - 1);
   R9Slot<D>& sl = slots[g];
@@ -101,6 +100,8 @@ void rule9_kernel(RuleArgs A) {
        base += (int64_t)gridDim.x * RPB) {
     const int64_t r = base + g;
     const bool valid = r < n;
+    double volo;
+    const DevParams& P = region_params<BATCH>(A, buf, valid ? r : start, volo);
     double c[D], h[D];
     int lvl = 0;
     if (valid) {
@@ -242,7 +243,7 @@ void rule9_kernel(RuleArgs A) {
     }
     __syncthreads();
     if (s == 0 && valid) {
-      const double vol = ldexp(A.vol_omega, -lvl);
+      const double vol = ldexp(volo, -lvl);
       const double S[8] = {f0,          ks_val(S2), ks_val(S3), ks_val(S4),
                            ks_val(S5), ks_val(S6), ks_val(S7), ks_val(S8)};
       RegionResult o;
@@ -301,7 +302,7 @@ void rule9_kernel(RuleArgs A) {
     }
     __syncthreads();
   }
-  block_partials(A, qs, es, nonfin);
+  if constexpr (!BATCH) block_partials(A, qs, es, nonfin);
 }
 
 #ifndef GM_RULE_FAMILY
@@ -312,27 +313,32 @@ void rule9_kernel(RuleArgs A) {
 #define GM_R9_CAT(a, b) GM_R9_CAT2(a, b)
 
 template <int D>
-static RuleKernelFn r9_pick() {
-  return rule9_kernel<D, GM_RULE_FAMILY, rule9_log2l(D)>;
+static RuleKernelFn r9_pick(bool batch) {
+  if constexpr (D <= kBatchMaxDim) {
+    if (batch) return rule9_kernel<D, GM_RULE_FAMILY, rule9_log2l(D), true>;
+  } else {
+    if (batch) return nullptr;
+  }
+  return rule9_kernel<D, GM_RULE_FAMILY, rule9_log2l(D), false>;
 }
 
-RuleKernelFn GM_R9_CAT(rule9_kernel_f, GM_RULE_FAMILY)(int d) {
+RuleKernelFn GM_R9_CAT(rule9_kernel_f, GM_RULE_FAMILY)(int d, bool batch) {
   switch (d) {
-    case 2: return r9_pick<2>();
-    case 3: return r9_pick<3>();
-    case 4: return r9_pick<4>();
-    case 5: return r9_pick<5>();
-    case 6: return r9_pick<6>();
-    case 7: return r9_pick<7>();
-    case 8: return r9_pick<8>();
-    case 9: return r9_pick<9>();
-    case 10: return r9_pick<10>();
-    case 11: return r9_pick<11>();
-    case 12: return r9_pick<12>();
-    case 13: return r9_pick<13>();
-    case 14: return r9_pick<14>();
-    case 15: return r9_pick<15>();
-    case 16: return r9_pick<16>();
+    case 2: return r9_pick<2>(batch);
+    case 3: return r9_pick<3>(batch);
+    case 4: return r9_pick<4>(batch);
+    case 5: return r9_pick<5>(batch);
+    case 6: return r9_pick<6>(batch);
+    case 7: return r9_pick<7>(batch);
+    case 8: return r9_pick<8>(batch);
+    case 9: return r9_pick<9>(batch);
+    case 10: return r9_pick<10>(batch);
+    case 11: return r9_pick<11>(batch);
+    case 12: return r9_pick<12>(batch);
+    case 13: return r9_pick<13>(batch);
+    case 14: return r9_pick<14>(batch);
+    case 15: return r9_pick<15>(batch);
+    case 16: return r9_pick<16>(batch);
     default: return nullptr;
   }
 }

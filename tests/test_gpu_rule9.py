@@ -132,3 +132,50 @@ def test_rule9_large_run_samples_match_oracle(fam, d, tau):
     full = O.rule_many(fam, p, act["c"][idx], act["h"][idx], act["lvl"][idx], 1.0, rule_id=R9)
     assert_regions_match(act["Q"][idx], act["err"][idx], act["axis"][idx], full,
                          "rule9 large sample")
+
+
+def _small_batch(n, seed, dmin=3, dmax=6, fams=(1, 2, 4, 3)):
+    rng = np.random.default_rng(seed)
+    out = [[] for _ in range(7)]
+    for i in range(n):
+        d = int(rng.integers(dmin, dmax + 1))
+        fam = int(fams[int(rng.integers(0, len(fams)))])
+        for lst, v in zip(out, (fam, W.family_params(fam, d, seed=seed * 100000 + i), d,
+                                np.zeros(d), np.ones(d), 10 ** rng.uniform(-8, -4), 1e-16)):
+            lst.append(v)
+    return out
+
+
+@pytest.mark.parametrize("graph_iters,model", [(0, 0), (4, 0), (0, 1)])
+def test_rule9_batch_matches_oracle_lockstep(graph_iters, model):
+    """Every item of a degree-9 batch: the oracle's lock-step batch with the
+    same rule gives the same status and I within 1e-12; sampled items equal
+    their own single-integral degree-9 runs."""
+    b = _small_batch(48, seed=11 + model)
+    gm.set_option("init_log2_regions", 6)
+    gm.set_option("graph_iters", graph_iters)
+    try:
+        print(f"case rule9 batch graph_iters={graph_iters} model={model}", flush=True)
+        with _Rule9(model):
+            rc, est, err, st = gm.integrate_batch(*b, 1 << 22)
+    finally:
+        gm.set_option("init_log2_regions", 12)
+        gm.set_option("graph_iters", 0)
+    orc, oest, oerr, ost, oits = O.integrate_batch(*b, 1 << 22, init_log2=6, rule_id=R9,
+                                                   err_model=model)
+    assert rc == orc
+    assert np.array_equal(st, ost)
+    assert np.all(np.abs(est - oest) <= I_TOL * np.abs(oest) + 1e-300)
+    for i in range(0, 48, 11):
+        gm.set_option("init_log2_regions", 6)
+        try:
+            with _Rule9(model):
+                I, E, s1 = gm.integrate(b[0][i], b[1][i], b[3][i], b[4][i], b[5][i], 1e-16,
+                                        1 << 22)
+                one = gm.last_stats()
+        finally:
+            gm.set_option("init_log2_regions", 12)
+        assert s1 == st[i]
+        assert abs(I - est[i]) <= I_TOL * abs(I), (i, I, est[i])
+        assert abs(E - err[i]) <= 1e-9 * E, (i, E, err[i])
+        assert one["evals"] == one["regions_evaluated"] * O.num_nodes9(b[2][i])
