@@ -389,11 +389,23 @@ def bench_grad(gm, W, closed_forms, tau: float, cap: int):
                  gm.integrate(4, pm, c["lo"], c["hi"], tau, 1e-16, cap)[0]) / 2e-6
     tf = time.perf_counter() - t0
     scale = np.abs(want).max()
+    # the same gradient with the degree-9 rule (forward tree and adjoint)
+    gm.set_option("rule", 2)
+    try:
+        gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
+        t0 = time.perf_counter()
+        I9, E9, g9, st9 = gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
+        t9 = time.perf_counter() - t0
+    finally:
+        gm.set_option("rule", 0)
     return {"d": d, "rel_tol": tau, "max_regions": cap, "status": st,
             "grad_s": tg, "fd_s": tf, "speedup": tf / tg,
             "integral_rel_err": abs(I - exact) / exact,
             "grad_max_err_rel_to_max": float(np.abs(g - want).max() / scale),
-            "fd_max_err_rel_to_max": float(np.abs(fd - want).max() / scale)}
+            "fd_max_err_rel_to_max": float(np.abs(fd - want).max() / scale),
+            "degree9": {"status": st9, "grad_s": t9, "speedup_vs_degree7_grad": tg / t9,
+                        "integral_rel_err": abs(I9 - exact) / exact,
+                        "grad_max_err_rel_to_max": float(np.abs(g9 - want).max() / scale)}}
 
 
 def main():

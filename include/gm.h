@@ -168,8 +168,9 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  *                        Genz-Malik rules embedded: 1 + 6d + 6d(d-1) +
  *                        8 C(d,3) + 2^d nodes, error estimate per
  *                        "err_model"), for gm_integrate and gm_eval_regions
- *                        with 2 <= d <= 16 and for gm_integrate_batch (every
- *                        item; d <= 10); gm_integrate_grad returns GM_EINVAL
+ *                        with 2 <= d <= 16, for gm_integrate_batch (every
+ *                        item; d <= 10) and for gm_integrate_grad (forward
+ *                        tree and adjoint with the degree-9 nodes and weights)
  *   "err_model"          error estimate of the degree-9 rule: 0 = vol |Q9 - Q7|
  *                        (default); 1 = the null-rule ratio test of Sec. 2's
  *                        heuristic-estimator reading: with n1 = |Q9 - Q7|,

@@ -1310,12 +1310,21 @@ void gmo_free(gmo_run* r) {
 /* ------------------------------------------------------------------------ */
 int gmo_quad_leaves(int fam, int d, const double* params, int64_t n, const double* c,
                     const double* h, const int32_t* lvl, double vol_omega, double* out_q) {
+  return gmo_quad_leaves_rule(fam, d, params, n, c, h, lvl, vol_omega, 0, out_q);
+}
+
+int gmo_quad_leaves_rule(int fam, int d, const double* params, int64_t n, const double* c,
+                         const double* h, const int32_t* lvl, double vol_omega, int rule,
+                         double* out_q) {
   ksum s = {0.0, 0.0};
   double out[16 + 32];
   int64_t i;
   int st = 0;
+  if (rule != 0 && rule != 2) return GMO_EINVAL;
   for (i = 0; i < n; ++i) {
-    if (gmo_rule(fam, d, params, c + i * d, h + i * d, lvl[i], vol_omega, out)) st = GMO_NONFINITE;
+    int rc = rule == 2 ? gmo_rule9(fam, d, params, c + i * d, h + i * d, lvl[i], vol_omega, 0, out)
+                       : gmo_rule(fam, d, params, c + i * d, h + i * d, lvl[i], vol_omega, out);
+    if (rc) st = GMO_NONFINITE;
     ks_add(&s, out[0]);
   }
   *out_q = ks_val(&s);
@@ -1325,7 +1334,7 @@ int gmo_quad_leaves(int fam, int d, const double* params, int64_t n, const doubl
 typedef struct {
   int fam, d;
   const double* p;
-  double w[5];
+  double w[8];
   ksum g[32];
 } grad_ctx;
 
@@ -1339,21 +1348,36 @@ static void grad_cb(void* pp, int cls, const double* x) {
 
 int gmo_grad_leaves(int fam, int d, const double* params, int64_t n, const double* c,
                     const double* h, const int32_t* lvl, double vol_omega, double* out_grad) {
-  double lam[5], v[5], e[5];
+  return gmo_grad_leaves_rule(fam, d, params, n, c, h, lvl, vol_omega, 0, out_grad);
+}
+
+/* The gradient of the fixed-tree quadrature with the degree-7 (rule 0) or
+   the degree-9 (rule 2) rule: the same nodes and weights as the rule. */
+int gmo_grad_leaves_rule(int fam, int d, const double* params, int64_t n, const double* c,
+                         const double* h, const int32_t* lvl, double vol_omega, int rule,
+                         double* out_grad) {
+  double lam[6], v[5], e[8];
   ksum tot[32];
   int64_t i;
   int j;
   grad_ctx q;
+  if (rule != 0 && rule != 2) return GMO_EINVAL;
   memset(tot, 0, sizeof tot);
   memset(&q, 0, sizeof q);
   q.fam = fam;
   q.d = d;
   q.p = params;
-  gmo_constants(d, lam, q.w, v, e);
+  if (rule == 2)
+    gmo_constants9(d, lam, q.w, e);
+  else
+    gmo_constants(d, lam, q.w, v, e);
   for (i = 0; i < n; ++i) {
     double vol = ldexp(vol_omega, -lvl[i]);
     memset(q.g, 0, sizeof q.g);
-    visit_nodes(d, c + i * d, h + i * d, grad_cb, &q);
+    if (rule == 2)
+      visit_nodes9(d, c + i * d, h + i * d, grad_cb, &q);
+    else
+      visit_nodes(d, c + i * d, h + i * d, grad_cb, &q);
     for (j = 0; j < 2 * d; ++j) ks_add(&tot[j], vol * ks_val(&q.g[j]));
   }
   for (j = 0; j < 2 * d; ++j) out_grad[j] = ks_val(&tot[j]);

@@ -157,6 +157,13 @@ int gmo_quad_leaves(int fam, int d, const double* params, int64_t n, const doubl
                     const double* h, const int32_t* lvl, double vol_omega, double* out_q);
 int gmo_grad_leaves(int fam, int d, const double* params, int64_t n, const double* c,
                     const double* h, const int32_t* lvl, double vol_omega, double* out_grad);
+/* The same with the rule chosen: 0 degree 7, 2 degree 9 (GMO_EINVAL otherwise). */
+int gmo_quad_leaves_rule(int fam, int d, const double* params, int64_t n, const double* c,
+                         const double* h, const int32_t* lvl, double vol_omega, int rule,
+                         double* out_q);
+int gmo_grad_leaves_rule(int fam, int d, const double* params, int64_t n, const double* c,
+                         const double* h, const int32_t* lvl, double vol_omega, int rule,
+                         double* out_grad);
 
 /* Lock-step batch of independent integrals sharing one region capacity. */
 int gmo_integrate_batch(int n, const int* fam, const double* params, const int* d,

@@ -92,6 +92,12 @@ def lib():
         L.gmo_grad_leaves.restype = C.c_int
         L.gmo_grad_leaves.argtypes = [C.c_int, C.c_int, dp, C.c_int64, dp, dp, i32p, C.c_double,
                                       dp]
+        L.gmo_quad_leaves_rule.restype = C.c_int
+        L.gmo_quad_leaves_rule.argtypes = [C.c_int, C.c_int, dp, C.c_int64, dp, dp, i32p,
+                                           C.c_double, C.c_int, dp]
+        L.gmo_grad_leaves_rule.restype = C.c_int
+        L.gmo_grad_leaves_rule.argtypes = [C.c_int, C.c_int, dp, C.c_int64, dp, dp, i32p,
+                                           C.c_double, C.c_int, dp]
         L.gmo_gk_constants.argtypes = [dp, dp, dp]
         L.gmo_gk_num_nodes.restype = C.c_int64
         L.gmo_gk_num_nodes.argtypes = [C.c_int]
@@ -368,37 +374,41 @@ def integrate(fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20, 
     return r.result()
 
 
-def quad_leaves(fam, params, c, h, lvl, vol_omega):
+def quad_leaves(fam, params, c, h, lvl, vol_omega, rule_id=0):
     c, cp = _d(c)
     h, hp = _d(h)
     lvl, lp = _i32(lvl)
     p, pp = _d(params)
     n, d = c.shape
     out = C.c_double()
-    rc = lib().gmo_quad_leaves(fam, d, pp, n, cp, hp, lp, float(vol_omega), C.byref(out))
+    rc = lib().gmo_quad_leaves_rule(fam, d, pp, n, cp, hp, lp, float(vol_omega), int(rule_id),
+                                    C.byref(out))
     return out.value, rc
 
 
-def grad_leaves(fam, params, c, h, lvl, vol_omega):
+def grad_leaves(fam, params, c, h, lvl, vol_omega, rule_id=0):
     c, cp = _d(c)
     h, hp = _d(h)
     lvl, lp = _i32(lvl)
     p, pp = _d(params)
     n, d = c.shape
     out = np.zeros(2 * d)
-    lib().gmo_grad_leaves(fam, d, pp, n, cp, hp, lp, float(vol_omega), _d(out)[1])
+    rc = lib().gmo_grad_leaves_rule(fam, d, pp, n, cp, hp, lp, float(vol_omega), int(rule_id),
+                                    _d(out)[1])
+    if rc != OK:
+        raise ValueError(f"oracle rejected rule {rule_id}")
     return out
 
 
 def integrate_grad(fam, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 20,
-                   init_log2=12, max_iters=10000):
+                   init_log2=12, max_iters=10000, rule_id=0, err_model=0):
     """Forward run with leaf retention, then the fixed-tree gradient."""
     r = Run(fam, params, lo, hi, rel_tol, abs_tol, max_regions, init_log2, max_iters,
-            keep_leaves=True)
+            keep_leaves=True, rule_id=rule_id, err_model=err_model)
     r.run()
     res = r.result()
     c, h, lvl = r.leaves()
-    res["grad"] = grad_leaves(fam, params, c, h, lvl, r.vol_omega)
+    res["grad"] = grad_leaves(fam, params, c, h, lvl, r.vol_omega, rule_id)
     res["leaves"] = (c, h, lvl)
     res["vol_omega"] = r.vol_omega
     return res

@@ -1,5 +1,6 @@
 // gm_adjoint.hip -- adjoint kernel of the gradient mode: the derivative of
-// the fixed-tree Genz-Malik quadrature with respect to (a, u).
+// the fixed-tree quadrature with respect to (a, u), for the degree-7
+// Genz-Malik rule or the degree-9 rule (its classes 6-8 added to the visit).
 //
 // The forward run (Sec. 3 loop) retains every retired region; together with
 // the last evaluated active set they form the frozen tree whose rule values
@@ -173,7 +174,55 @@ __device__ __forceinline__ void visit_nodes(const RuleConsts& K, const double (&
   }
 }
 
-template <int D, int FAM>
+// The degree-9 rule's further classes, in its order: +-l6 e_i (weight index
+// 5), +-l2 e_i +- l3 e_j for ordered pairs i != j (6), +-l4 (e_i +- e_j +- e_k)
+// for i < j < k (7).
+template <int D, typename Fn>
+__device__ __forceinline__ void visit_nodes9_extra(const RuleConsts& K, const double (&c)[D],
+                                                   const double (&h)[D], Fn&& fn) {
+  double x[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) x[k] = c[k];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    x[i] = fma(K.lam6, h[i], c[i]);
+    fn(5, x);
+    x[i] = fma(-K.lam6, h[i], c[i]);
+    fn(5, x);
+    x[i] = c[i];
+  }
+  for (int i = 0; i < D; ++i) {
+    for (int j = 0; j < D; ++j) {
+      if (j == i) continue;
+      for (int sg = 0; sg < 4; ++sg) {
+        const double si = (sg & 2) ? -K.lam2 : K.lam2;
+        const double sj = (sg & 1) ? -K.lam3 : K.lam3;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+          x[k] = (k == i) ? fma(si, h[k], c[k]) : ((k == j) ? fma(sj, h[k], c[k]) : c[k]);
+        fn(6, x);
+      }
+    }
+  }
+  for (int i = 0; i < D - 2; ++i) {
+    for (int j = i + 1; j < D - 1; ++j) {
+      for (int l = j + 1; l < D; ++l) {
+        for (int sg = 0; sg < 8; ++sg) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const double sk = (k == i)   ? ((sg & 1) ? -K.lam4 : K.lam4)
+                              : (k == j) ? ((sg & 2) ? -K.lam4 : K.lam4)
+                                         : ((sg & 4) ? -K.lam4 : K.lam4);
+            x[k] = (k == i || k == j || k == l) ? fma(sk, h[k], c[k]) : c[k];
+          }
+          fn(7, x);
+        }
+      }
+    }
+  }
+}
+
+template <int D, int FAM, bool R9>
 __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(AdjArgs A) {
   dd tot[2 * D];
 #pragma unroll
@@ -186,9 +235,18 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(AdjArgs A) {
     double acc[2 * D];
 #pragma unroll
     for (int j = 0; j < 2 * D; ++j) acc[j] = 0.0;
-    visit_nodes<D>(A.K, c, h, [&](int cls, const double (&x)[D]) {
-      adj_node<D, FAM>(A.P, x, A.K.w[cls], acc);
-    });
+    if constexpr (R9) {
+      visit_nodes<D>(A.K, c, h, [&](int cls, const double (&x)[D]) {
+        adj_node<D, FAM>(A.P, x, A.K.w9[cls], acc);
+      });
+      visit_nodes9_extra<D>(A.K, c, h, [&](int cls, const double (&x)[D]) {
+        adj_node<D, FAM>(A.P, x, A.K.w9[cls], acc);
+      });
+    } else {
+      visit_nodes<D>(A.K, c, h, [&](int cls, const double (&x)[D]) {
+        adj_node<D, FAM>(A.P, x, A.K.w[cls], acc);
+      });
+    }
     double g[2 * D];
     adj_finish<D, FAM>(A.P, vol, acc, g);
 #pragma unroll
@@ -216,32 +274,32 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(AdjArgs A) {
 #endif
 
 template <int D>
-static AdjFn adj_d() {
+static AdjFn adj_d(bool r9) {
   constexpr int F = GM_FAMILY;
-  if constexpr (F >= 1 && F <= 6) return adjoint_kernel<D, F>;
+  if constexpr (F >= 1 && F <= 6) return r9 ? adjoint_kernel<D, F, true> : adjoint_kernel<D, F, false>;
   return nullptr;
 }
 
 #define GM_CAT2(a, b) a##b
 #define GM_CAT(a, b) GM_CAT2(a, b)
 
-AdjFn GM_CAT(adjoint_kernel_f, GM_FAMILY)(int d) {
+AdjFn GM_CAT(adjoint_kernel_f, GM_FAMILY)(int d, bool r9) {
   switch (d) {
-    case 2: return adj_d<2>();
-    case 3: return adj_d<3>();
-    case 4: return adj_d<4>();
-    case 5: return adj_d<5>();
-    case 6: return adj_d<6>();
-    case 7: return adj_d<7>();
-    case 8: return adj_d<8>();
-    case 9: return adj_d<9>();
-    case 10: return adj_d<10>();
-    case 11: return adj_d<11>();
-    case 12: return adj_d<12>();
-    case 13: return adj_d<13>();
-    case 14: return adj_d<14>();
-    case 15: return adj_d<15>();
-    case 16: return adj_d<16>();
+    case 2: return adj_d<2>(r9);
+    case 3: return adj_d<3>(r9);
+    case 4: return adj_d<4>(r9);
+    case 5: return adj_d<5>(r9);
+    case 6: return adj_d<6>(r9);
+    case 7: return adj_d<7>(r9);
+    case 8: return adj_d<8>(r9);
+    case 9: return adj_d<9>(r9);
+    case 10: return adj_d<10>(r9);
+    case 11: return adj_d<11>(r9);
+    case 12: return adj_d<12>(r9);
+    case 13: return adj_d<13>(r9);
+    case 14: return adj_d<14>(r9);
+    case 15: return adj_d<15>(r9);
+    case 16: return adj_d<16>(r9);
     default: return nullptr;
   }
 }

@@ -18,13 +18,14 @@ struct AdjArgs {
 };
 
 using AdjFn = void (*)(AdjArgs);
-// One per family translation unit; nullptr for the polynomial (no parameters).
-AdjFn adjoint_kernel_f1(int d);
-AdjFn adjoint_kernel_f2(int d);
-AdjFn adjoint_kernel_f3(int d);
-AdjFn adjoint_kernel_f4(int d);
-AdjFn adjoint_kernel_f5(int d);
-AdjFn adjoint_kernel_f6(int d);
-AdjFn adjoint_kernel_f7(int d);
+// One per family translation unit (r9: the degree-9 rule's nodes and weights);
+// nullptr for the polynomial (no parameters).
+AdjFn adjoint_kernel_f1(int d, bool r9);
+AdjFn adjoint_kernel_f2(int d, bool r9);
+AdjFn adjoint_kernel_f3(int d, bool r9);
+AdjFn adjoint_kernel_f4(int d, bool r9);
+AdjFn adjoint_kernel_f5(int d, bool r9);
+AdjFn adjoint_kernel_f6(int d, bool r9);
+AdjFn adjoint_kernel_f7(int d, bool r9);
 
 }  // namespace gm

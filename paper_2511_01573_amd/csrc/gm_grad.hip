@@ -30,14 +30,14 @@ __global__ void adjoint_reduce_kernel(const double* partials, int np, int nparam
   out[j] = dd_val(v);
 }
 
-static AdjFn adj_fn(int d, int fam) {
+static AdjFn adj_fn(int d, int fam, bool r9) {
   switch (fam) {
-    case 1: return adjoint_kernel_f1(d);
-    case 2: return adjoint_kernel_f2(d);
-    case 3: return adjoint_kernel_f3(d);
-    case 4: return adjoint_kernel_f4(d);
-    case 5: return adjoint_kernel_f5(d);
-    case 6: return adjoint_kernel_f6(d);
+    case 1: return adjoint_kernel_f1(d, r9);
+    case 2: return adjoint_kernel_f2(d, r9);
+    case 3: return adjoint_kernel_f3(d, r9);
+    case 4: return adjoint_kernel_f4(d, r9);
+    case 5: return adjoint_kernel_f5(d, r9);
+    case 6: return adjoint_kernel_f6(d, r9);
     default: return nullptr;
   }
 }
@@ -53,7 +53,8 @@ extern "C" int gm_integrate_grad(int integrand_id, const double* params, int d, 
   int rc = validate(integrand_id, params, d, lo, hi, rel_tol, abs_tol);
   if (rc != GM_OK) return rc;
   if (!out_est || !out_err || !out_grad) return GM_EINVAL;
-  if (options().rule != 0) return GM_EINVAL;  // the adjoint is written for the Genz-Malik rule
+  // the adjoint covers the Genz-Malik rules (degree 7 and 9), not Gauss-Kronrod
+  if (options().rule == 1) return GM_EINVAL;
   std::lock_guard<std::mutex> lk(api_mutex());
   hipStream_t s = (hipStream_t)stream;
   RunResult rr;
@@ -85,7 +86,7 @@ extern "C" int gm_integrate_grad(int integrand_id, const double* params, int d, 
       if (part) (void)hipFree(part);
       return GM_ENOMEM;
     }
-    AdjFn fn = adj_fn(d, integrand_id);
+    AdjFn fn = adj_fn(d, integrand_id, options().rule == 2);
     A.partials = part;
     A.R = RegionSrc{lv.C, lv.H, lv.L, nullptr, lv.cap, 0, 0};
     A.n = n1;

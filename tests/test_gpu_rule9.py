@@ -179,3 +179,27 @@ def test_rule9_batch_matches_oracle_lockstep(graph_iters, model):
         assert abs(I - est[i]) <= I_TOL * abs(I), (i, I, est[i])
         assert abs(E - err[i]) <= 1e-9 * E, (i, E, err[i])
         assert one["evals"] == one["regions_evaluated"] * O.num_nodes9(b[2][i])
+
+
+@pytest.mark.parametrize("fam,d,tau,model", [(4, 3, 1e-9, 0), (1, 4, 1e-8, 1), (2, 3, 1e-8, 0),
+                                             (3, 4, 1e-8, 0), (5, 3, 1e-6, 0)])
+def test_rule9_gradient_matches_oracle(fam, d, tau, model):
+    """Gradient mode with the degree-9 rule: the frozen tree is the oracle's,
+    and the adjoint over it matches the oracle's fixed-tree gradient with the
+    degree-9 nodes and weights to 1e-12 of the largest component."""
+    p = W.family_params(fam, d, seed=800 * fam + d)
+    lo, hi = W.unit_box(d)
+    gm.set_option("init_log2_regions", 6)
+    try:
+        print(f"case rule9 grad fam={fam} d={d} tau={tau} model={model}", flush=True)
+        with _Rule9(model):
+            I, E, g, st = gm.integrate_grad(fam, p, lo, hi, tau, 1e-16, 1 << 20)
+    finally:
+        gm.set_option("init_log2_regions", 12)
+    ref = O.integrate_grad(fam, p, lo, hi, tau, 1e-16, 1 << 20, 6, rule_id=R9, err_model=model)
+    assert st == ref["status"]
+    assert abs(I - ref["I"]) <= I_TOL * abs(ref["I"])
+    assert np.max(np.abs(g - ref["grad"])) <= 1e-12 * np.max(np.abs(ref["grad"]))
+    if fam == 4:
+        want = np.array([float(x) for x in CF.gaussian_grad(p[:d], p[d:])])
+        assert np.abs(g - want).max() <= 1e-7 * np.abs(want).max()

@@ -333,3 +333,31 @@ def test_degree9_fewer_evaluations_on_a_smooth_integrand():
     assert r7["status"] == r9["status"] == O.OK
     assert abs(r9["I"] - exact) <= 10 * tau * abs(exact)
     assert r9["evals"] < r7["evals"]
+
+
+def test_degree9_tree_quadrature_and_gradient():
+    """Over the degree-9 frozen tree: the quadrature of the leaves equals the
+    run's estimate, and the gradient of that fixed-tree quadrature matches
+    central differences of the same quadrature (h = 1e-6) and, for the
+    Gaussian, the erf closed form to the run's accuracy."""
+    from paper_2511_01573_amd import workloads as W
+    d, fam = 3, cf.GAUSSIAN
+    p = W.family_params(fam, d, 21)
+    res = O.integrate_grad(fam, p, np.zeros(d), np.ones(d), 1e-10, 1e-16, 1 << 20, 3,
+                           rule_id=O.DEGREE9)
+    c, h, lvl = res["leaves"]
+    q, rc = O.quad_leaves(fam, p, c, h, lvl, res["vol_omega"], rule_id=O.DEGREE9)
+    assert rc == 0 and abs(q - res["I"]) <= 1e-14 * abs(q)
+    g = res["grad"]
+    for j in range(2 * d):
+        e = np.zeros(2 * d)
+        e[j] = 1e-6
+        qp, _ = O.quad_leaves(fam, p + e, c, h, lvl, res["vol_omega"], rule_id=O.DEGREE9)
+        qm, _ = O.quad_leaves(fam, p - e, c, h, lvl, res["vol_omega"], rule_id=O.DEGREE9)
+        fd = (qp - qm) / 2e-6
+        assert abs(g[j] - fd) <= 1e-7 * np.abs(g).max(), (j, g[j], fd)
+    want = np.array([float(x) for x in cf.gaussian_grad(p[:d], p[d:])])
+    assert np.abs(g - want).max() <= 1e-8 * np.abs(want).max()
+    # the degree-7 weights on the degree-9 tree give a different (less exact) gradient
+    g7 = O.grad_leaves(fam, p, c, h, lvl, res["vol_omega"], 0)
+    assert np.abs(g7 - g).max() > 0
