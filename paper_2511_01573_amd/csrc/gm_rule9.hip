@@ -230,22 +230,20 @@ void rule9_kernel(RuleArgs A) {
       }
       corner_sweep<D, FAM, LOG2L>(P, t5p, t5m, (uint32_t)s, S5);
     }
-    // Combine the L lanes of the region.
+    // Combine the L lanes of the region: each lane's compensated class sums
+    // are rounded once and added across the lanes in a butterfly (a + b and
+    // b + a round alike, so every lane ends with the same totals).
+    double T[7] = {ks_val(S2), ks_val(S3), ks_val(S4), ks_val(S5),
+                   ks_val(S6), ks_val(S7), ks_val(S8)};
 #pragma unroll
     for (int m = L / 2; m >= 1; m >>= 1) {
-      S2 = ks_merge(S2, shfl_xor_ks(S2, m));
-      S3 = ks_merge(S3, shfl_xor_ks(S3, m));
-      S4 = ks_merge(S4, shfl_xor_ks(S4, m));
-      S5 = ks_merge(S5, shfl_xor_ks(S5, m));
-      S6 = ks_merge(S6, shfl_xor_ks(S6, m));
-      S7 = ks_merge(S7, shfl_xor_ks(S7, m));
-      S8 = ks_merge(S8, shfl_xor_ks(S8, m));
+#pragma unroll
+      for (int q = 0; q < 7; ++q) T[q] = T[q] + __shfl_xor(T[q], m, 64);
     }
     __syncthreads();
     if (s == 0 && valid) {
       const double vol = ldexp(volo, -lvl);
-      const double S[8] = {f0,          ks_val(S2), ks_val(S3), ks_val(S4),
-                           ks_val(S5), ks_val(S6), ks_val(S7), ks_val(S8)};
+      const double S[8] = {f0, T[0], T[1], T[2], T[3], T[4], T[5], T[6]};
       RegionResult o;
       o.nonfinite = 0;
 #pragma unroll
