@@ -257,6 +257,6 @@ RuleKernelFn rule9_kernel_f4(int d, bool batch);
 RuleKernelFn rule9_kernel_f5(int d, bool batch);
 RuleKernelFn rule9_kernel_f6(int d, bool batch);
 RuleKernelFn rule9_kernel_f7(int d, bool batch);
-constexpr int rule9_log2l(int d) { return d - 4 < 2 ? 2 : (d - 4 > 6 ? 6 : d - 4); }
+constexpr int rule9_log2l(int d) { return d - 5 < 2 ? 2 : (d - 5 > 6 ? 6 : d - 5); }
 
 }  // namespace gm

@@ -36,6 +36,9 @@ namespace gm {
 template <int D>
 struct R9Slot {
   double c[D], h[D], tc[D], pc[D], dv[D], sc[D];
+  // per-coordinate terms at the perturbed positions: [0] +l2, [1] -l2,
+  // [2] +l3 (= +l4), [3] -l3, [4] +l6, [5] -l6
+  double tp[6][D];
 };
 
 // Work-item tables: the axis pairs (i, j) and triples (i, j, k), packed 4
@@ -129,6 +132,12 @@ void rule9_kernel(RuleArgs A) {
       if ((k & (L - 1)) == s) {
         sl.tc[k] = tc[k];
         sl.pc[k] = pc;
+        sl.tp[0][k] = F::term(P, k, fma(K.lam2, h[k], c[k]));
+        sl.tp[1][k] = F::term(P, k, fma(-K.lam2, h[k], c[k]));
+        sl.tp[2][k] = F::term(P, k, fma(K.lam3, h[k], c[k]));
+        sl.tp[3][k] = F::term(P, k, fma(-K.lam3, h[k], c[k]));
+        sl.tp[4][k] = F::term(P, k, fma(K.lam6, h[k], c[k]));
+        sl.tp[5][k] = F::term(P, k, fma(-K.lam6, h[k], c[k]));
       }
       pc = (k == 0) ? tc[0] : F::comb(pc, tc[k]);
     }
@@ -140,10 +149,8 @@ void rule9_kernel(RuleArgs A) {
     // wavefront stay on the same code path.
     // Axes: +-l2, +-l3, +-l6 along axis i and its fourth difference.
     for (int i = s; i < D; i += L) {
-      const double ci = sl.c[i], hi = sl.h[i];
-      const double v[6] = {F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci)),
-                           F::term(P, i, fma(K.lam3, hi, ci)), F::term(P, i, fma(-K.lam3, hi, ci)),
-                           F::term(P, i, fma(K.lam6, hi, ci)), F::term(P, i, fma(-K.lam6, hi, ci))};
+      const double v[6] = {sl.tp[0][i], sl.tp[1][i], sl.tp[2][i],
+                           sl.tp[3][i], sl.tp[4][i], sl.tp[5][i]};
       const double pci = sl.pc[i];
       double x[6], f[6];
 #pragma unroll
@@ -162,12 +169,10 @@ void rule9_kernel(RuleArgs A) {
     for (int it = s; it < NPAIR; it += L) {
       const int pk = kItems<D>.pair[it];
       const int i = pk & 15, j = pk >> 4;
-      const double ci = sl.c[i], hi = sl.h[i], cj = sl.c[j], hj = sl.h[j];
       // x_i at +l3, -l3 (= +-l4), +l2, -l2
-      const double ti[4] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci)),
-                            F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci))};
-      const double tj3[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
-      const double tj2[2] = {F::term(P, j, fma(K.lam2, hj, cj)), F::term(P, j, fma(-K.lam2, hj, cj))};
+      const double ti[4] = {sl.tp[2][i], sl.tp[3][i], sl.tp[0][i], sl.tp[1][i]};
+      const double tj3[2] = {sl.tp[2][j], sl.tp[3][j]};
+      const double tj2[2] = {sl.tp[0][j], sl.tp[1][j]};
       const double pci = sl.pc[i];
       double m[4];
 #pragma unroll
@@ -194,12 +199,9 @@ void rule9_kernel(RuleArgs A) {
     for (int it = s; it < NTRI; it += L) {
       const int tk3 = kItems<D>.tri[it];
       const int i = tk3 & 15, j = (tk3 >> 4) & 15, k = tk3 >> 8;
-      const double ci = sl.c[i], hi = sl.h[i];
-      const double cj = sl.c[j], hj = sl.h[j];
-      const double ck = sl.c[k], hk = sl.h[k];
-      const double ti[2] = {F::term(P, i, fma(K.lam4, hi, ci)), F::term(P, i, fma(-K.lam4, hi, ci))};
-      const double tj[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
-      const double tk[2] = {F::term(P, k, fma(K.lam4, hk, ck)), F::term(P, k, fma(-K.lam4, hk, ck))};
+      const double ti[2] = {sl.tp[2][i], sl.tp[3][i]};
+      const double tj[2] = {sl.tp[2][j], sl.tp[3][j]};
+      const double tk[2] = {sl.tp[2][k], sl.tp[3][k]};
       const double pci = sl.pc[i];
       double m1[2], m2[4], x8[8], f8[8];
 #pragma unroll
