@@ -775,6 +775,15 @@ LeafView leaf_view() { return LeafView{g_leaves.C, g_leaves.H, g_leaves.L, g_lea
 
 static int leaf_reserve(int d, int64_t need, int64_t have, hipStream_t s) {
   if (need <= g_leaves.cap && g_leaves.d == d) return GM_OK;
+  // A store of another dimension holds nothing to keep: free it first and
+  // size the new one from this run's need alone (doubling its capacity would
+  // compound over calls that alternate dimensions).
+  if (g_leaves.d != d) {
+    GM_HIP(hipStreamSynchronize(s));
+    g_leaves.release();
+    g_leaves.d = d;
+    have = 0;
+  }
   int64_t nc = std::max<int64_t>(need, std::max<int64_t>(1 << 16, 2 * g_leaves.cap));
   double *C = nullptr, *H = nullptr;
   uint16_t* L = nullptr;
@@ -787,7 +796,7 @@ static int leaf_reserve(int d, int64_t need, int64_t have, hipStream_t s) {
     if (L) (void)hipFree(L);
     return GM_ENOMEM;
   }
-  if (have > 0 && g_leaves.d == d) {
+  if (have > 0) {
     for (int j = 0; j < d; ++j) {
       GM_HIP(hipMemcpyAsync(C + j * nc, g_leaves.C + j * g_leaves.cap, sizeof(double) * have,
                             hipMemcpyDeviceToDevice, s));

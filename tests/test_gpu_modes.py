@@ -137,3 +137,17 @@ def test_batch_shared_capacity_and_invalid_items():
                                                    [1e-3, 1e-10], [1e-16] * 2, 3000, init_log2=4)
     assert list(st[:2]) == list(ost) == [gm.OK, gm.MAX_REGIONS]
     assert np.all(np.abs(est[:2] - oest) <= I_TOL * np.abs(oest))
+
+
+def test_grad_calls_alternating_dimension_keep_the_leaf_store_bounded():
+    """Regression: the gradient mode's leaf store is reallocated when the
+    dimension changes; its size must come from the run's need, not double the
+    previous store's (which compounded over calls alternating d and ran the
+    device out of memory).  32 calls alternate d = 2 and d = 3."""
+    for k in range(32):
+        d = 2 + (k & 1)
+        p = W.family_params(4, d, seed=900 + k)
+        lo, hi = W.unit_box(d)
+        I, E, g, st = gm.integrate_grad(4, p, lo, hi, 1e-6, 1e-16, 1 << 16)
+        assert st == gm.OK, (k, st)
+        assert np.all(np.isfinite(g))
