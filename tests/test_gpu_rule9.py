@@ -17,8 +17,9 @@ pytestmark = pytest.mark.gpu
 
 R9 = O.DEGREE9
 # regions per case: several blocks of the kernel's launch and a ragged tail
-# (regions per block: 64 for d = 2..7, then 32, 16, 8, 4, 4 for d = 8, 9, 10, 12, 16)
-SIZES = {2: 203, 3: 197, 4: 150, 5: 133, 6: 129, 7: 101, 8: 83, 9: 37, 10: 29, 12: 11, 16: 5}
+# (regions per block: 64 for d = 2..7, then 32, 16, 8 for d = 8, 9, 10 and 4 above)
+SIZES = {2: 203, 3: 197, 4: 150, 5: 133, 6: 129, 7: 101, 8: 83, 9: 37, 10: 29, 11: 13, 12: 11, 13: 7,
+         14: 6, 15: 5, 16: 5}
 
 
 class _Rule9:

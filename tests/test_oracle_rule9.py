@@ -361,3 +361,23 @@ def test_degree9_tree_quadrature_and_gradient():
     # the degree-7 weights on the degree-9 tree give a different (less exact) gradient
     g7 = O.grad_leaves(fam, p, c, h, lvl, res["vol_omega"], 0)
     assert np.abs(g7 - g).max() > 0
+
+
+def test_degree9_batch_items_equal_independent_runs():
+    """The oracle's lock-step batch with the degree-9 rule: below the shared
+    budget every item is bitwise its own independent run."""
+    from paper_2511_01573_amd import workloads as W
+    fams, ds = [4, 1, 2, 3, 5, 4], [2, 3, 4, 5, 3, 6]
+    ps = [W.family_params(f, d, 40 + i) for i, (f, d) in enumerate(zip(fams, ds))]
+    lo = [np.zeros(d) for d in ds]
+    hi = [np.ones(d) for d in ds]
+    taus = [1e-9, 1e-8, 1e-7, 1e-7, 1e-5, 1e-6]
+    for model in (0, 1):
+        rc, est, err, st, its = O.integrate_batch(fams, ps, ds, lo, hi, taus, [1e-16] * 6, 1 << 22,
+                                                  init_log2=4, rule_id=O.DEGREE9,
+                                                  err_model=model)
+        for i in range(6):
+            r = O.integrate(fams[i], ps[i], lo[i], hi[i], taus[i], 1e-16, 1 << 22, 4,
+                            rule_id=O.DEGREE9, err_model=model)
+            assert (est[i], err[i], st[i], its[i]) == (r["I"], r["E"], r["status"],
+                                                       r["iterations"])
