@@ -122,7 +122,8 @@ int gm_integrate_grad(int integrand_id, const double* params, int d, const doubl
 
 /*
  * gm_eval_regions -- the rule kernel alone on a caller-given region list
- * (Sec. 2: rule value, error estimate and split axis of each region).
+ * (Sec. 2: rule value, error estimate and split axis of each region), with
+ * the rule and error model the options "rule" and "err_model" select.
  *   c, h        host double[n*d], row-major: region r is prod_j [c - h, c + h]
  *   lvl         host int32[n]: region volume = vol(box [lo, hi]) * 2^-lvl
  *   out_q, out_err  host double[n]; out_axis host int32[n] (bit 7 set when

@@ -77,8 +77,9 @@ __device__ __forceinline__ void chain_n(double (&x)[N], const double* tc, int k0
   }
 }
 
-// Three wavefronts per SIMD up to d = 10 (a few values spill to scratch, and
-// the extra wavefront hides more latency); two above, where the spill grows.
+// Three wavefronts per SIMD up to d = 10 (at most a few values spill to
+// scratch, and the extra wavefront hides more latency); two above, where the
+// spill would grow.
 template <int D, int FAM, int LOG2L, bool BATCH>
 __global__ __launch_bounds__(kRuleBlock) __attribute__((amdgpu_waves_per_eu(D <= 10 ? 3 : 2)))
 void rule9_kernel(RuleArgs A) {
