@@ -204,3 +204,35 @@ def test_rule9_gradient_matches_oracle(fam, d, tau, model):
     if fam == 4:
         want = np.array([float(x) for x in CF.gaussian_grad(p[:d], p[d:])])
         assert np.abs(g - want).max() <= 1e-7 * np.abs(want).max()
+
+
+def test_rule9_general_box_and_iteration_budget():
+    """A box other than the unit cube (vol_omega != 1) and a run stopped by the
+    iteration budget: status, iterations, regions, I and the final active set
+    as the oracle's."""
+    fam, d = 4, 3
+    p = W.family_params(fam, d, seed=33)
+    lo, hi = np.array([-0.5, 0.25, -1.0]), np.array([1.5, 1.0, 0.75])
+    for max_iters in (3, 10000):
+        gm.set_option("init_log2_regions", 3)
+        gm.set_option("max_iters", max_iters)
+        try:
+            print(f"case rule9 box max_iters={max_iters}", flush=True)
+            with _Rule9(0):
+                I, E, st = gm.integrate(fam, p, lo, hi, 1e-11, 1e-16, 1 << 20)
+                stats = gm.last_stats()
+                act = gm.last_active(d)
+        finally:
+            gm.set_option("init_log2_regions", 12)
+            gm.set_option("max_iters", 10000)
+        run = O.Run(fam, p, lo, hi, 1e-11, 1e-16, 1 << 20, 3, max_iters, rule_id=R9)
+        run.run()
+        ref = run.result()
+        assert st == ref["status"] == (gm.MAX_ITERS if max_iters == 3 else gm.OK)
+        assert stats["iterations"] == ref["iterations"]
+        assert stats["regions_evaluated"] == ref["regions"]
+        assert abs(I - ref["I"]) <= I_TOL * abs(ref["I"])
+        ra = run.active()
+        assert np.array_equal(act["c"], ra["c"]) and np.array_equal(act["h"], ra["h"])
+        full = O.rule_many(fam, p, ra["c"], ra["h"], ra["lvl"], run.vol_omega, rule_id=R9)
+        assert_regions_match(act["Q"], act["err"], act["axis"], full, "rule9 general box")
