@@ -161,9 +161,10 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  *                        tensor-product Gauss-Kronrod rule (Sec. 3: 7-point
  *                        Gauss / 15-point Kronrod per axis, 15^d nodes,
  *                        err = vol |Q_K - Q_G|), for gm_integrate and
- *                        gm_eval_regions with 2 <= d <= 6 (GM_EINVAL above;
- *                        gm_integrate_batch and gm_integrate_grad return
- *                        GM_EINVAL while it is selected); 2 = the degree-9
+ *                        gm_eval_regions with 2 <= d <= 6 (GM_EINVAL above),
+ *                        and for gm_integrate_batch (items of d > 6 get
+ *                        GM_EINVAL); gm_integrate_grad returns GM_EINVAL while
+ *                        it is selected; 2 = the degree-9
  *                        fully symmetric rule (the "9-order" rule of Sec. 2,
  *                        read as degree 9 with the degree-7 and degree-5
  *                        Genz-Malik rules embedded: 1 + 6d + 6d(d-1) +

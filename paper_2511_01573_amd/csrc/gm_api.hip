@@ -646,15 +646,15 @@ RuleKernelFn rule_kernel(int d, int fam, int log2l, bool batch) {
   }
 }
 
-RuleKernelFn gk_kernel(int d, int fam) {
+RuleKernelFn gk_kernel(int d, int fam, bool batch) {
   switch (fam) {
-    case 1: return gk_kernel_f1(d);
-    case 2: return gk_kernel_f2(d);
-    case 3: return gk_kernel_f3(d);
-    case 4: return gk_kernel_f4(d);
-    case 5: return gk_kernel_f5(d);
-    case 6: return gk_kernel_f6(d);
-    case 7: return gk_kernel_f7(d);
+    case 1: return gk_kernel_f1(d, batch);
+    case 2: return gk_kernel_f2(d, batch);
+    case 3: return gk_kernel_f3(d, batch);
+    case 4: return gk_kernel_f4(d, batch);
+    case 5: return gk_kernel_f5(d, batch);
+    case 6: return gk_kernel_f6(d, batch);
+    case 7: return gk_kernel_f7(d, batch);
     default: return nullptr;
   }
 }
@@ -695,7 +695,7 @@ int64_t nodes_per_region(int d) {
 }
 
 hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s) {
-  RuleKernelFn fn = log2l == kMapGk    ? gk_kernel(d, fam)
+  RuleKernelFn fn = log2l == kMapGk    ? gk_kernel(d, fam, false)
                     : log2l >= kMapR9 ? r9_kernel(d, fam, false)
                                       : rule_kernel(d, fam, log2l, false);
   if (!fn) return hipErrorInvalidValue;

@@ -15,7 +15,7 @@
 // One iteration (a fixed launch sequence, replayed from a hipGraph):
 //   rule      one launch per (d, family) group, the group range read on the
 //             device (tile shape per group from the tuning table; the
-//             degree-9 rule, option rule = 2, uses its own lane mapping)
+//             degree-9 and Gauss-Kronrod rules use their own mappings)
 //   reduce    one workgroup per chunk: double-double sums of Q and err
 //   finalize  one wavefront per item: I, E over its chunks, T, stopping rule
 //   classify  one workgroup per chunk: retire test, in-chunk ballot ranks,
@@ -604,7 +604,6 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
               double* out_est, double* out_err, int* out_status, hipStream_t s) {
   const auto t_start = std::chrono::steady_clock::now();
   const Options& opt = options();
-  if (opt.rule == 1) return GM_EINVAL;  // the Gauss-Kronrod rule is for single integrals
   if (opt.prune != 0) return GM_EINVAL;  // the batch's shared capacity has its own rule
   // Per-item offsets into the packed inputs and validation.
   std::vector<int64_t> poff(n), boff(n);
@@ -777,9 +776,10 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
     ra.VOL = (const double*)(base + lay.vol);
     ra.grp = A.group_range + 2 * g;
     ra.bbuf = &A.bst->buf;
-    if (opt.rule == 2) {
-      // degree 9: the kernel's own lane mapping, a fixed grid-stride grid
-      rfn[g] = r9_kernel(gd[g], gfam[g], true);
+    if (opt.rule != 0) {
+      // degree 9 or Gauss-Kronrod: the kernel's own mapping, a fixed
+      // grid-stride grid (items of d > 6 are invalid under Gauss-Kronrod)
+      rfn[g] = opt.rule == 2 ? r9_kernel(gd[g], gfam[g], true) : gk_kernel(gd[g], gfam[g], true);
       rgrid[g] = 2048;
     } else {
       const Tile t = tile_for(gd[g], gfam[g]);

@@ -237,14 +237,14 @@ constexpr int kBatchMaxDim = kTprMaxDim;  // batch items have 2 <= d <= 10
 constexpr int kRuleBlockSize = 256;
 
 // Tensor-product Gauss-Kronrod rule kernels (one wavefront per region), one
-// launcher per family, 2 <= d <= kGkMaxDim.
-RuleKernelFn gk_kernel_f1(int d);
-RuleKernelFn gk_kernel_f2(int d);
-RuleKernelFn gk_kernel_f3(int d);
-RuleKernelFn gk_kernel_f4(int d);
-RuleKernelFn gk_kernel_f5(int d);
-RuleKernelFn gk_kernel_f6(int d);
-RuleKernelFn gk_kernel_f7(int d);
+// launcher per family, 2 <= d <= kGkMaxDim (batch: the batch-store variant).
+RuleKernelFn gk_kernel_f1(int d, bool batch);
+RuleKernelFn gk_kernel_f2(int d, bool batch);
+RuleKernelFn gk_kernel_f3(int d, bool batch);
+RuleKernelFn gk_kernel_f4(int d, bool batch);
+RuleKernelFn gk_kernel_f5(int d, bool batch);
+RuleKernelFn gk_kernel_f6(int d, bool batch);
+RuleKernelFn gk_kernel_f7(int d, bool batch);
 constexpr int kGkMaxDim = 6;
 
 // Degree-9 fully symmetric rule kernels, one launcher per family, 2 <= d <= 16

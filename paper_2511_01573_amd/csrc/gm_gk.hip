@@ -80,14 +80,13 @@ __device__ __forceinline__ void gk_contract(const DevParams& P, const double (*t
   }
 }
 
-template <int D, int FAM>
+template <int D, int FAM, bool BATCH>
 __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
   using F = Fam<FAM>;
   int64_t start, end;
   int buf;
-  if (!active_range<false>(A, start, end, buf)) return;
-  const RegionSrc R = region_src<false>(A, buf);
-  const DevParams& P = A.P;
+  if (!active_range<BATCH>(A, start, end, buf)) return;
+  const RegionSrc R = region_src<BATCH>(A, buf);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ double tt[kGkRegionsPerBlock][D][15];
   dd qs = {0.0, 0.0}, es = {0.0, 0.0};
@@ -97,6 +96,8 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
        base += (int64_t)gridDim.x * kGkRegionsPerBlock) {
     const int64_t r = base + wv;
     const bool ok = r < end;
+    double volo;
+    const DevParams& P = region_params<BATCH>(A, buf, ok ? r : start, volo);
     double c[D], h[D];
     int lvl = 0;
     if (ok) {
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
 #pragma unroll
     for (int i = 0; i < D; ++i) tm[i] = dd_val(wave_sum_dd(dd{sm[i], 0.0}));
     if (ok && lane == 0) {
-      const double vol = ldexp(A.vol_omega, -lvl);
+      const double vol = ldexp(volo, -lvl);
       const double QK = dd_val(ta), QG = dd_val(tb);
       RegionResult o;
       o.q = vol * QK;
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
     }
     __syncthreads();
   }
-  block_partials(A, qs, es, nonfin);
+  if constexpr (!BATCH) block_partials(A, qs, es, nonfin);
 }
 
 #ifndef GM_RULE_FAMILY
@@ -197,14 +198,14 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
 #define GM_GK_CAT2(a, b) a##b
 #define GM_GK_CAT(a, b) GM_GK_CAT2(a, b)
 
-RuleKernelFn GM_GK_CAT(gk_kernel_f, GM_RULE_FAMILY)(int d) {
+RuleKernelFn GM_GK_CAT(gk_kernel_f, GM_RULE_FAMILY)(int d, bool batch) {
   constexpr int F = GM_RULE_FAMILY;
   switch (d) {
-    case 2: return rule_gk_kernel<2, F>;
-    case 3: return rule_gk_kernel<3, F>;
-    case 4: return rule_gk_kernel<4, F>;
-    case 5: return rule_gk_kernel<5, F>;
-    case 6: return rule_gk_kernel<6, F>;
+    case 2: return batch ? rule_gk_kernel<2, F, true> : rule_gk_kernel<2, F, false>;
+    case 3: return batch ? rule_gk_kernel<3, F, true> : rule_gk_kernel<3, F, false>;
+    case 4: return batch ? rule_gk_kernel<4, F, true> : rule_gk_kernel<4, F, false>;
+    case 5: return batch ? rule_gk_kernel<5, F, true> : rule_gk_kernel<5, F, false>;
+    case 6: return batch ? rule_gk_kernel<6, F, true> : rule_gk_kernel<6, F, false>;
     default: return nullptr;
   }
 }

@@ -64,6 +64,8 @@ int choose_mapping(int d, int64_t n);
 RuleKernelFn rule_kernel(int d, int fam, int log2l, bool batch);
 // Degree-9 rule kernel of (d, family): single-store or batch-store variant.
 RuleKernelFn r9_kernel(int d, int fam, bool batch);
+// Gauss-Kronrod rule kernel of (d, family), d <= kGkMaxDim.
+RuleKernelFn gk_kernel(int d, int fam, bool batch);
 // Nodes of the rule the options select.
 int64_t nodes_per_region(int d);
 bool mapping_allowed(int d, int log2l);

@@ -88,6 +88,7 @@ def test_gk_paper_gaussian_d3_closed_form():
 
 
 def test_gk_rejects_unsupported_calls():
+    """d = 7 single integrals and the gradient mode are refused."""
     lo, hi = W.unit_box(7)
     p = W.family_params(4, 7, seed=1)
     gm.set_option("rule", 1)
@@ -98,9 +99,43 @@ def test_gk_rejects_unsupported_calls():
         p3 = W.family_params(4, 3, seed=1)
         with pytest.raises(gm.GMError):
             gm.integrate_grad(4, p3, lo3, hi3, 1e-6, 1e-16, 1 << 20)
-        with pytest.raises(gm.GMError):
-            gm.integrate_batch([4], [p3], [3], [lo3], [hi3], [1e-6], [1e-16], 1 << 20)
     finally:
         gm.set_option("rule", 0)
     with pytest.raises(gm.GMError):
         gm.set_option("rule", 3)
+
+
+def test_gk_batch_matches_oracle_lockstep():
+    """A batch run with the Gauss-Kronrod rule: per item the oracle's lock-step
+    batch with the same rule (same status, I within 1e-12); an item of d = 7
+    is invalid under this rule."""
+    rng = np.random.default_rng(5)
+    fams, ps, ds, los, his, rts = [], [], [], [], [], []
+    for i in range(24):
+        d = int(rng.integers(2, 5))
+        fam = int((1, 2, 4, 3)[int(rng.integers(0, 4))])
+        fams.append(fam)
+        ps.append(W.family_params(fam, d, seed=3000 + i))
+        ds.append(d)
+        los.append(np.zeros(d))
+        his.append(np.ones(d))
+        rts.append(10 ** rng.uniform(-9, -5))
+    fams.append(4)
+    ps.append(W.family_params(4, 7, seed=1))
+    ds.append(7)
+    los.append(np.zeros(7))
+    his.append(np.ones(7))
+    rts.append(1e-6)
+    ats = [1e-16] * len(fams)
+    gm.set_option("init_log2_regions", 2)
+    try:
+        print("case gk batch", flush=True)
+        rc, est, err, st = _with_gk(gm.integrate_batch, fams, ps, ds, los, his, rts, ats, 1 << 20)
+    finally:
+        gm.set_option("init_log2_regions", 12)
+    assert st[-1] == gm.EINVAL and np.isnan(est[-1])
+    orc, oest, oerr, ost, oits = O.integrate_batch(fams[:-1], ps[:-1], ds[:-1], los[:-1], his[:-1],
+                                                   rts[:-1], ats[:-1], 1 << 20, init_log2=2,
+                                                   rule_id=GK)
+    assert np.array_equal(st[:-1], ost)
+    assert np.all(np.abs(est[:-1] - oest) <= I_TOL * np.abs(oest))
