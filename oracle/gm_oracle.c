@@ -1269,9 +1269,11 @@ int64_t gmo_leaf_count(const gmo_run* r) { return r->nleaf + r->n; }
 
 void gmo_get_leaves(const gmo_run* r, double* c, double* h, int32_t* lvl) {
   int d = r->d;
-  memcpy(c, r->lc, sizeof(double) * r->nleaf * d);
-  memcpy(h, r->lh, sizeof(double) * r->nleaf * d);
-  memcpy(lvl, r->llvl, sizeof(int32_t) * r->nleaf);
+  if (r->nleaf > 0) { /* no leaf list is allocated before the first retirement */
+    memcpy(c, r->lc, sizeof(double) * r->nleaf * d);
+    memcpy(h, r->lh, sizeof(double) * r->nleaf * d);
+    memcpy(lvl, r->llvl, sizeof(int32_t) * r->nleaf);
+  }
   memcpy(c + r->nleaf * d, r->c, sizeof(double) * r->n * d);
   memcpy(h + r->nleaf * d, r->h, sizeof(double) * r->n * d);
   memcpy(lvl + r->nleaf, r->lvl, sizeof(int32_t) * r->n);
