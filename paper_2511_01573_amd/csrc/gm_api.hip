@@ -815,6 +815,17 @@ static int leaf_reserve(int d, int64_t need, int64_t have, hipStream_t s) {
   return GM_OK;
 }
 
+// Pinned host copy of the status block: the host's status reads and the
+// initial write are direct DMA transfers instead of staged pageable copies.
+static Status* pinned_status() {
+  static Status* p = nullptr;
+  if (!p && hipHostMalloc((void**)&p, sizeof(Status), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  return p;
+}
+
 // One adaptive run on the device (gm_integrate and the forward pass of
 // gm_integrate_grad).  On return the status block holds the final state.
 int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,
@@ -904,7 +915,13 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   hst.rel_tol = rel_tol;
   hst.abs_tol = abs_tol;
   hst.prune_on = g_opt.prune;
-  GM_HIP(hipMemcpyAsync(st, &hst, sizeof hst, hipMemcpyHostToDevice, s));
+  Status* const pin = pinned_status();
+  if (pin) {
+    *pin = hst;
+    GM_HIP(hipMemcpyAsync(st, pin, sizeof hst, hipMemcpyHostToDevice, s));
+  } else {
+    GM_HIP(hipMemcpyAsync(st, &hst, sizeof hst, hipMemcpyHostToDevice, s));
+  }
   {
     int g = (int)std::min<int64_t>((n0 + 255) / 256, 4096);
     hipLaunchKernelGGL(init_kernel, dim3(g), dim3(256), 0, s, ia);
@@ -972,8 +989,9 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       if (phases) GM_HIP(hipEventRecord(ev[k][4], s));
       nb = std::min<int64_t>(cap, 2 * nb);
     }
-    GM_HIP(hipMemcpyAsync(&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(pin ? (void*)pin : (void*)&hst, st, sizeof hst, hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
+    if (pin) hst = *pin;
     const int ran = (int)std::min<int64_t>(K, hst.iter - iter_done);
     if (ran <= 0 && !hst.done) {
       // the status block did not advance: never loop on it
