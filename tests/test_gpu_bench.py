@@ -1,0 +1,37 @@
+"""The benchmark's JSON line on a short run: one line with the metric, the
+roofline object of the rule kernel (bound, achieved, peak, unit, frac,
+traffic) and the CPU-oracle baseline (value, unit, cores, kind, sample)."""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_line_has_the_contract_fields():
+    print("case bench short run", flush=True)
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "1", "--warmup",
+                        "0", "--no-modes", "--taus", "1e-3,1e-5", "--cpu-seconds", "1"],
+                       capture_output=True, text=True, timeout=110)
+    assert p.returncode == 0, p.stderr[-2000:]
+    lines = [l for l in p.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    out = json.loads(lines[0])
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config"):
+        assert k in out, k
+    assert out["n_gpus"] == 1 and out["steps"] == 1 and out["dtype"] == "f64"
+    assert out["value"] > 0 and "workload" in out["config"]
+    r = out["roofline"]
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert 0 < r["frac"] < 1 and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
+    assert "traffic" in r
+    cb = out["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] == 1 and cb["value"] > 0 and cb["sample"]
