@@ -128,25 +128,31 @@ def run_cases(gm, cases):
 
 def cpu_baseline(budget_s: float):
     """The serial oracle on a bounded sample: the d = 8 cases at rel_tol 1e-3
-    and 1e-5 (full runs), in family order, until the budget is spent."""
+    and 1e-5 (full runs), in family order, passes over them repeated while the
+    budget lasts (all passes counted)."""
     from oracle import oracle as O
     from paper_2511_01573_amd import workloads as W
     cases = W.config2(taus=(1e-3, 1e-5))
     evals = 0
     secs = 0.0
     names = []
-    for c in cases:
-        if secs >= budget_s:
-            break
-        t0 = time.perf_counter()
-        r = O.integrate(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"], c["abs_tol"],
-                        c["max_regions"])
-        secs += time.perf_counter() - t0
-        evals += r["evals"]
-        names.append(c["name"])
+    passes = 0
+    while secs < budget_s:
+        for c in cases:
+            if secs >= budget_s:
+                break
+            t0 = time.perf_counter()
+            r = O.integrate(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"],
+                            c["abs_tol"], c["max_regions"])
+            secs += time.perf_counter() - t0
+            evals += r["evals"]
+            if passes == 0:
+                names.append(c["name"])
+        passes += 1
     return {"value": evals / secs, "unit": "integrand evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(names)} full oracle runs of the d=8 workload at rel_tol 1e-3/1e-5 "
-                      f"({', '.join(names)}); {evals} evals in {secs:.1f} s, serial C, 1 thread"}
+            "sample": f"{passes} pass(es) over {len(names)} full oracle runs of the d=8 workload at "
+                      f"rel_tol 1e-3/1e-5 ({', '.join(names)}); {evals} evals in {secs:.1f} s, "
+                      f"serial C, 1 thread"}
 
 
 def bench_batch(gm, W, closed_forms):
