@@ -236,3 +236,34 @@ def test_rule9_general_box_and_iteration_budget():
         assert np.array_equal(act["c"], ra["c"]) and np.array_equal(act["h"], ra["h"])
         full = O.rule_many(fam, p, ra["c"], ra["h"], ra["lvl"], run.vol_omega, rule_id=R9)
         assert_regions_match(act["Q"], act["err"], act["axis"], full, "rule9 general box")
+
+
+@pytest.mark.parametrize("rule_id", [O.DEGREE9, O.GAUSS_KRONROD])
+def test_other_rules_status_codes_match_oracle(rule_id):
+    """The non-finite and precision-limit stops under the degree-9 and
+    Gauss-Kronrod rules: the corner peak with a = (-1, -1) on [0,1]^2 is
+    infinite at cell centres of the initial grid (both rules evaluate the
+    centre); a nearly constant integrand with rel_tol 0 ends when every
+    region's error falls below the resolution of |I|."""
+    cases = [(3, np.array([-1.0, -1.0, 0.0, 0.0]), 2, 1e-6, 1e-16, gm.NONFINITE),
+             (4, np.array([1e-3] * 3 + [0.5] * 3), 3, 0.0, 1e-300, gm.PRECISION_LIMIT)]
+    for fam, p, d, tau, atol, want in cases:
+        lo, hi = W.unit_box(d)
+        gm.set_option("rule", int(rule_id))
+        gm.set_option("init_log2_regions", 4)
+        try:
+            print(f"case rule{rule_id} status fam={fam} d={d}", flush=True)
+            I, E, st = gm.integrate(fam, p, lo, hi, tau, atol, 1 << 20)
+            stats = gm.last_stats()
+        finally:
+            gm.set_option("rule", 0)
+            gm.set_option("init_log2_regions", 12)
+        run = O.Run(fam, p, lo, hi, tau, atol, 1 << 20, 4, 10000, rule_id=int(rule_id))
+        run.run()
+        ref = run.result()
+        assert st == ref["status"] == want, (st, ref)
+        assert stats["iterations"] == ref["iterations"]
+        if want == gm.NONFINITE:
+            assert np.isnan(I) and np.isnan(E)
+        else:
+            assert abs(I - ref["I"]) <= I_TOL * abs(ref["I"])
