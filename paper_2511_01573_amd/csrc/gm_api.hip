@@ -672,13 +672,13 @@ RuleKernelFn r9_kernel(int d, int fam, bool batch) {
   }
 }
 
-// Mapping codes: the Gauss-Kronrod kernel (one wavefront per region), and the
+// Mapping codes: the Gauss-Kronrod kernel (gk_threads(d) per region), and the
 // degree-9 kernel with 2^(code - kMapR9) lanes per region.
 constexpr int kMapGk = 100;
 constexpr int kMapR9 = 200;
 
-int lanes_of_mapping(int map) {
-  return map == kMapGk ? 64 : map >= kMapR9 ? (1 << (map - kMapR9)) : map < 0 ? 1 : (1 << map);
+int lanes_of_mapping(int map, int d) {
+  return map == kMapGk ? gk_threads(d) : map >= kMapR9 ? (1 << (map - kMapR9)) : map < 0 ? 1 : (1 << map);
 }
 
 int64_t nodes_per_region(int d) {
@@ -738,8 +738,8 @@ int choose_mapping(int d, int64_t n) {
   return best;
 }
 
-int rule_grid(int log2l, int64_t n) {
-  const int64_t per_block = log2l == kMapGk    ? kRuleBlockSize / 64
+int rule_grid(int log2l, int64_t n, int d) {
+  const int64_t per_block = log2l == kMapGk    ? kRuleBlockSize / gk_threads(d)
                             : log2l >= kMapR9 ? (kRuleBlockSize >> (log2l - kMapR9))
                             : (log2l < 0)   ? kRuleBlockSize
                                             : (kRuleBlockSize >> log2l);
@@ -962,9 +962,9 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
     int64_t nb = n;
     for (int k = 0; k < K; ++k) {
       const int map = choose_mapping(d, nb);
-      const int rg = rule_grid(map, nb);
+      const int rg = rule_grid(map, nb, d);
       const int tg = tile_grid_for(nb);
-      g_stats.lanes_per_region = lanes_of_mapping(map);
+      g_stats.lanes_per_region = lanes_of_mapping(map, d);
       if (timing) GM_HIP(hipEventRecord(ev[k][0], s));
       GM_HIP(launch_rule(d, fam, map, ra, rg, s));
       if (timing) GM_HIP(hipEventRecord(ev[k][1], s));
@@ -1134,7 +1134,7 @@ int gm_eval_regions(int integrand_id, const double* params, int d, const double*
   GM_HIP(hipMemcpyAsync((void*)ra.H[0], hs.data(), sizeof(double) * d * n, hipMemcpyHostToDevice, s));
   GM_HIP(hipMemcpyAsync((void*)ra.L[0], ls.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, s));
   const int map = choose_mapping(d, n);
-  GM_HIP(launch_rule(d, integrand_id, map, ra, rule_grid(map, n), s));
+  GM_HIP(launch_rule(d, integrand_id, map, ra, rule_grid(map, n, d), s));
   std::vector<uint8_t> ax((size_t)n);
   GM_HIP(hipMemcpyAsync(out_q, ra.Q, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   GM_HIP(hipMemcpyAsync(out_err, ra.ERR, sizeof(double) * n, hipMemcpyDeviceToHost, s));

@@ -236,7 +236,11 @@ constexpr int kTprMaxDim = 10;
 constexpr int kBatchMaxDim = kTprMaxDim;  // batch items have 2 <= d <= 10
 constexpr int kRuleBlockSize = 256;
 
-// Tensor-product Gauss-Kronrod rule kernels (one wavefront per region), one
+// Threads of the Gauss-Kronrod kernel per region: one wavefront up to d = 3, the
+// whole workgroup from d = 4 on (15^d nodes per region).
+constexpr int gk_threads(int d) { return d >= 4 ? kRuleBlockSize : 64; }
+
+// Tensor-product Gauss-Kronrod rule kernels (gk_threads(d) per region), one
 // launcher per family, 2 <= d <= kGkMaxDim (batch: the batch-store variant).
 RuleKernelFn gk_kernel_f1(int d, bool batch);
 RuleKernelFn gk_kernel_f2(int d, bool batch);

@@ -11,20 +11,27 @@
 // band (relative to vol times the Kronrod sum of |f|), widest half-width, then
 // lowest index; geometry guard as for that rule.
 //
-// Mapping: one wavefront per region, four regions per workgroup.  Lane l takes
-// the index pairs (k_0, k_1) = l, l + 64, ... of the first two axes' 225 pairs;
-// the remaining axes are contracted inside the lane one axis at a time (sum
+// Mapping: up to d = 3 one wavefront per region (four regions per workgroup),
+// lane l taking the index pairs (k_0, k_1) = l, l + 64, ... of the first two
+// axes' 225 pairs; from d = 4 on a whole workgroup per region, thread t taking
+// the triples t, t + 256, ... of the first three axes' 3375.  The remaining
+// axes are contracted inside the thread one axis at a time (sum
 // factorisation): a level returns its all-Kronrod sum, all-Gauss sum, Kronrod
 // sum of |f| and, for each deeper axis i, the sum with Gauss weights on axis i
 // alone.  The per-axis terms T_j(c_j + x_k h_j) are tabulated once per region
 // in LDS; every node argument is the left-to-right chain of the terms, as in
-// the Genz-Malik kernel.  Lane sums are combined with double-double shuffles.
+// the Genz-Malik kernel.  Thread sums are combined with double-double
+// shuffles within a wavefront and through LDS across wavefronts.
 #include "gm_family.hpp"
 #include "gm_gk_table.hpp"
 
 namespace gm {
 
-constexpr int kGkRegionsPerBlock = kRuleBlock / 64;
+// Leading axes whose index tuples are spread over a region's gk_threads(d)
+// threads: the 225 pairs of axes 0, 1 for one wavefront, the 3375 triples of
+// axes 0, 1, 2 for a whole workgroup.
+template <int D>
+constexpr int gk_spread_axes() { return gk_threads(D) > 64 ? 3 : 2; }
 
 template <int D>
 struct GkSums {
@@ -83,18 +90,25 @@ __device__ __forceinline__ void gk_contract(const DevParams& P, const double (*t
 template <int D, int FAM, bool BATCH>
 __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
   using F = Fam<FAM>;
+  constexpr int NT = gk_threads(D);  // threads per region
+  constexpr int RPB = kRuleBlock / NT;  // regions per block step
+  constexpr int SPREAD = gk_spread_axes<D>();
+  constexpr int NTUPLE = SPREAD == 3 ? 3375 : 225;
+  constexpr int NW = NT / 64;  // wavefronts per region
   int64_t start, end;
   int buf;
   if (!active_range<BATCH>(A, start, end, buf)) return;
   const RegionSrc R = region_src<BATCH>(A, buf);
+  const int slot = threadIdx.x / NT, t = threadIdx.x % NT;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __shared__ double tt[kGkRegionsPerBlock][D][15];
+  __shared__ double tt[RPB][D][15];
+  __shared__ dd red[kRuleBlock / 64][3 + D];  // per-wavefront partial sums
   dd qs = {0.0, 0.0}, es = {0.0, 0.0};
   int nonfin = 0;
   // The trip count depends on the workgroup only, so the barriers are uniform.
-  for (int64_t base = start + (int64_t)blockIdx.x * kGkRegionsPerBlock; base < end;
-       base += (int64_t)gridDim.x * kGkRegionsPerBlock) {
-    const int64_t r = base + wv;
+  for (int64_t base = start + (int64_t)blockIdx.x * RPB; base < end;
+       base += (int64_t)gridDim.x * RPB) {
+    const int64_t r = base + slot;
     const bool ok = r < end;
     double volo;
     const DevParams& P = region_params<BATCH>(A, buf, ok ? r : start, volo);
@@ -109,59 +123,96 @@ __global__ __launch_bounds__(kRuleBlock) void rule_gk_kernel(RuleArgs A) {
         h[j] = 0.0;
       }
     }
-    if (ok && lane < 15) {
-      const double xk = gk::kX[lane];
+    if (ok && t < 15) {
+      const double xk = gk::kX[t];
 #pragma unroll
-      for (int j = 0; j < D; ++j) tt[wv][j][lane] = F::term(P, j, fma(xk, h[j], c[j]));
+      for (int j = 0; j < D; ++j) tt[slot][j][t] = F::term(P, j, fma(xk, h[j], c[j]));
     }
     __syncthreads();
     double sa = 0.0, sb = 0.0, sab = 0.0, sm[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) sm[i] = 0.0;
     if (ok) {
-      for (int o = lane; o < 225; o += 64) {
-        const int k0 = o / 15, k1 = o - 15 * k0;
-        const double s = F::comb(tt[wv][0][k0], tt[wv][1][k1]);
-        GkSums<D> g;
-        if constexpr (D == 2) {
-          const double f = F::template outer<D>(P, s);
-          g.a = f;
-          g.b = f;
-          g.abs_a = fabs(f);
-        } else {
-          gk_contract<D, FAM, 2>(P, tt[wv], s, g);
-        }
-        const double wk0 = gk::kWK[k0], wk1 = gk::kWK[k1];
-        const double wg0 = gk::kWG[k0], wg1 = gk::kWG[k1];
-        const double wkk = wk0 * wk1;
-        sa = fma(wkk, g.a, sa);
-        sb = fma(wg0 * wg1, g.b, sb);
-        sab = fma(wkk, g.abs_a, sab);
-        sm[0] = fma(wg0 * wk1, g.a, sm[0]);
-        sm[1] = fma(wk0 * wg1, g.a, sm[1]);
+      for (int o = t; o < NTUPLE; o += NT) {
+        if constexpr (SPREAD == 2) {
+          const int k0 = o / 15, k1 = o - 15 * k0;
+          const double s = F::comb(tt[slot][0][k0], tt[slot][1][k1]);
+          GkSums<D> g;
+          if constexpr (D == 2) {
+            const double f = F::template outer<D>(P, s);
+            g.a = f;
+            g.b = f;
+            g.abs_a = fabs(f);
+          } else {
+            gk_contract<D, FAM, 2>(P, tt[slot], s, g);
+          }
+          const double wk0 = gk::kWK[k0], wk1 = gk::kWK[k1];
+          const double wg0 = gk::kWG[k0], wg1 = gk::kWG[k1];
+          const double wkk = wk0 * wk1;
+          sa = fma(wkk, g.a, sa);
+          sb = fma(wg0 * wg1, g.b, sb);
+          sab = fma(wkk, g.abs_a, sab);
+          sm[0] = fma(wg0 * wk1, g.a, sm[0]);
+          sm[1] = fma(wk0 * wg1, g.a, sm[1]);
 #pragma unroll
-        for (int i = 2; i < D; ++i) sm[i] = fma(wkk, g.m[i], sm[i]);
+          for (int i = 2; i < D; ++i) sm[i] = fma(wkk, g.m[i], sm[i]);
+        } else {
+          const int k0 = o / 225, k12 = o - 225 * k0;
+          const int k1 = k12 / 15, k2 = k12 - 15 * k1;
+          const double s =
+              F::comb(F::comb(tt[slot][0][k0], tt[slot][1][k1]), tt[slot][2][k2]);
+          GkSums<D> g;
+          gk_contract<D, FAM, 3>(P, tt[slot], s, g);
+          const double wk0 = gk::kWK[k0], wk1 = gk::kWK[k1], wk2 = gk::kWK[k2];
+          const double wg0 = gk::kWG[k0], wg1 = gk::kWG[k1], wg2 = gk::kWG[k2];
+          const double wkkk = (wk0 * wk1) * wk2;
+          sa = fma(wkkk, g.a, sa);
+          sb = fma((wg0 * wg1) * wg2, g.b, sb);
+          sab = fma(wkkk, g.abs_a, sab);
+          sm[0] = fma((wg0 * wk1) * wk2, g.a, sm[0]);
+          sm[1] = fma((wk0 * wg1) * wk2, g.a, sm[1]);
+          sm[2] = fma((wk0 * wk1) * wg2, g.a, sm[2]);
+#pragma unroll
+          for (int i = 3; i < D; ++i) sm[i] = fma(wkkk, g.m[i], sm[i]);
+        }
       }
     }
-    const dd ta = wave_sum_dd(dd{sa, 0.0});
-    const dd tb = wave_sum_dd(dd{sb, 0.0});
-    const dd tab = wave_sum_dd(dd{sab, 0.0});
-    double tm[D];
+    // Sums over the region's threads: double-double within each wavefront,
+    // then across the region's wavefronts through LDS.
+    dd tot[3 + D];
+    tot[0] = wave_sum_dd(dd{sa, 0.0});
+    tot[1] = wave_sum_dd(dd{sb, 0.0});
+    tot[2] = wave_sum_dd(dd{sab, 0.0});
 #pragma unroll
-    for (int i = 0; i < D; ++i) tm[i] = dd_val(wave_sum_dd(dd{sm[i], 0.0}));
-    if (ok && lane == 0) {
+    for (int i = 0; i < D; ++i) tot[3 + i] = wave_sum_dd(dd{sm[i], 0.0});
+    if constexpr (NW > 1) {
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 3 + D; ++q) red[wv][q] = tot[q];
+      }
+      __syncthreads();
+      if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < 3 + D; ++q) {
+          dd v = red[slot * NW][q];
+          for (int w = 1; w < NW; ++w) v = dd_sum(v, red[slot * NW + w][q]);
+          tot[q] = v;
+        }
+      }
+    }
+    if (ok && t == 0) {
       const double vol = ldexp(volo, -lvl);
-      const double QK = dd_val(ta), QG = dd_val(tb);
+      const double QK = dd_val(tot[0]), QG = dd_val(tot[1]);
       RegionResult o;
       o.q = vol * QK;
       o.err = vol * fabs(QK - QG);
       double e[D], emax = -1.0;
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        e[i] = vol * fabs(QK - tm[i]);
+        e[i] = vol * fabs(QK - dd_val(tot[3 + i]));
         emax = e[i] > emax ? e[i] : emax;
       }
-      const double thr = emax - A.K.axis_band * (vol * dd_val(tab));
+      const double thr = emax - A.K.axis_band * (vol * dd_val(tot[2]));
       int axis = -1;
       double hb = 0.0, cb = 0.0;
 #pragma unroll

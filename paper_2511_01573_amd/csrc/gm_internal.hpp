@@ -69,7 +69,7 @@ RuleKernelFn gk_kernel(int d, int fam, bool batch);
 // Nodes of the rule the options select.
 int64_t nodes_per_region(int d);
 bool mapping_allowed(int d, int log2l);
-int rule_grid(int log2l, int64_t n);
+int rule_grid(int log2l, int64_t n, int d);
 int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,
                  double rel_tol, double abs_tol, int64_t max_regions, hipStream_t s,
                  bool keep_leaves, RunResult* out);
