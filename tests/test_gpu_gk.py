@@ -139,3 +139,21 @@ def test_gk_batch_matches_oracle_lockstep():
                                                    rule_id=GK)
     assert np.array_equal(st[:-1], ost)
     assert np.all(np.abs(est[:-1] - oest) <= I_TOL * np.abs(oest))
+
+
+@pytest.mark.parametrize("fam,d,n", [(4, 3, 70000), (2, 4, 40000), (3, 5, 20000)])
+def test_gk_rule_kernel_grid_stride_sampled(fam, d, n):
+    """More regions than one pass of the grid covers (16384 workgroups of
+    four regions up to d = 3, of one region from d = 4 on), so every
+    workgroup loops: a sample of the regions, spread over the whole range,
+    against the oracle, and every region's Q finite and err >= 0."""
+    p = W.family_params(fam, d, seed=700 * fam + d)
+    lo, hi = W.unit_box(d)
+    c, h, lvl = W.random_regions(d, n, seed=13 * d + fam)
+    print(f"case gk grid-stride fam={fam} d={d} n={n}", flush=True)
+    gq, ge, gax = _with_gk(gm.eval_regions, fam, p, lo, hi, c, h, lvl)
+    assert np.all(np.isfinite(gq)) and np.all(ge >= 0.0)
+    idx = np.unique(np.concatenate([np.arange(8), n - 8 + np.arange(8),
+                                    np.random.default_rng(d).integers(0, n, 48)]))
+    ref = O.rule_many(fam, p, c[idx], h[idx], lvl[idx], 1.0, rule_id=GK)
+    assert_regions_match(gq[idx], ge[idx], gax[idx], ref, f"gk grid-stride fam{fam} d{d}")
