@@ -21,8 +21,9 @@ struct Fam {
     if constexpr (FAM == kOsc || FAM == kCornerPeak) {
       return P.a[j] * x;
     } else if constexpr (FAM == kProductPeak) {
+      // the per-axis factor itself, so a node costs only the chain of products
       const double t = x - P.u[j];
-      return P.inv_a2[j] + t * t;
+      return fm::rcp(P.inv_a2[j] + t * t);
     } else if constexpr (FAM == kGaussian) {
       const double t = P.a[j] * (x - P.u[j]);
       return t * t;
@@ -92,7 +93,8 @@ struct Fam {
       for (int i = 0; i < N; ++i) a[i] = P.c0 + s[i];
       fm::cos_n<N>(a, f);
     } else if constexpr (FAM == kProductPeak) {
-      fm::rcp_n<N>(s, f);
+#pragma unroll
+      for (int i = 0; i < N; ++i) f[i] = s[i];
     } else if constexpr (FAM == kCornerPeak) {
 #pragma unroll
       for (int i = 0; i < N; ++i) a[i] = cpk_power<D>(s[i]);
