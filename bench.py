@@ -252,8 +252,9 @@ def bench_config3(gm, W, closed_forms, log2cap: int):
 def bench_gk(gm, W, closed_forms):
     """The tensor-product Gauss-Kronrod rule (7-point Gauss / 15-point
     Kronrod per axis) against the Genz-Malik rule on the same integrals, both
-    from an initial partition of 2^3 cells: time to tolerance, evaluations
-    and accuracy against the closed form."""
+    from an initial partition of 2^3 cells: time to tolerance, evaluations,
+    rule-kernel throughput (a second, timed run) and accuracy against the
+    closed form."""
     cases = []
     c1 = W.config1()
     cases.append(("gaussian_d3_a5", c1["family"], c1["params"], 3, 1e-6))
@@ -274,12 +275,19 @@ def bench_gk(gm, W, closed_forms):
                 I, E, st = gm.integrate(fam, p, lo, hi, tau, 1e-16, 1 << 24)
                 dt = time.perf_counter() - t0
                 s = gm.last_stats()
+                gm.set_option("timing", 1)
+                try:
+                    gm.integrate(fam, p, lo, hi, tau, 1e-16, 1 << 24)
+                    rule_ms = gm.last_stats()["rule_ms"]
+                finally:
+                    gm.set_option("timing", 0)
             finally:
                 gm.set_option("rule", 0)
                 gm.set_option("init_log2_regions", 12)
             key = "gk" if rule else "gm"
             row[key] = {"status": st, "seconds": dt, "evals": s["evals"],
                         "regions": s["regions_evaluated"], "evals_per_s": s["evals"] / dt,
+                        "rule_evals_per_s": s["evals"] / max(rule_ms * 1e-3, 1e-12),
                         "rel_err_vs_closed_form": abs(I - ex) / abs(ex)}
         out.append(row)
     return out
