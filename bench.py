@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--rule", type=int, default=0, choices=(0, 2),
                     help="rule of the timed suite: 0 degree 7 (the benchmark), 2 degree 9 "
                          "(profiling runs; its line carries no FLOP roofline)")
+    ap.add_argument("--only", choices=("batch", "grad"), default=None,
+                    help="run one mode by itself (a warm-up and one timed call), for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -423,6 +425,37 @@ def bench_grad(gm, W, closed_forms, tau: float, cap: int):
                         "grad_max_err_rel_to_max": float(np.abs(g9 - want).max() / scale)}}
 
 
+def run_only(gm, W, mode: str, grad_tau: float, grad_cap: int):
+    """One mode by itself, for a kernel trace that holds nothing else: the
+    4096-integral batch (one warm-up and one timed gm_integrate_batch call,
+    as in the batch section) or the d = 8 Gaussian gradient (one warm-up and
+    one timed gm_integrate_grad call, as in the gradient section)."""
+    import torch
+    if mode == "batch":
+        b = W.config4()
+        args = (b["families"], b["params"], b["ds"], b["los"], b["his"], b["rel_tols"], b["abs_tols"])
+        gm.set_option("graph_iters", 8)
+        try:
+            gm.integrate_batch(*args, 1 << 28)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, est, err, st = gm.integrate_batch(*args, 1 << 28)
+            dt = time.perf_counter() - t0
+        finally:
+            gm.set_option("graph_iters", 0)
+        return {"mode": "batch", "integrals": len(b["families"]), "seconds": dt,
+                "evals": gm.last_stats()["evals"],
+                "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
+    c = W.config5()
+    gm.integrate_grad(4, c["params"], c["lo"], c["hi"], grad_tau, 1e-16, grad_cap)
+    t0 = time.perf_counter()
+    I, E, g, st = gm.integrate_grad(4, c["params"], c["lo"], c["hi"], grad_tau, 1e-16, grad_cap)
+    dt = time.perf_counter() - t0
+    s = gm.last_stats()
+    return {"mode": "grad", "d": 8, "rel_tol": grad_tau, "seconds": dt, "status": st,
+            "evals": s["evals"], "regions": s["regions_evaluated"]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -435,6 +468,9 @@ def main():
     import torch
     from paper_2511_01573_amd import gm, workloads as W
 
+    if args.only:
+        print(json.dumps(run_only(gm, W, args.only, args.grad_tau, 1 << args.grad_log2cap)))
+        return
     taus = tuple(float(x) for x in args.taus.split(","))
     cases = W.config2(taus=taus)
     gm.set_option("timing", 1)

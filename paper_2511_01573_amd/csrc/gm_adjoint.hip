@@ -9,6 +9,16 @@
 // with the nodes and weights of the rule kernel (Sec. 2).  Per family the
 // node derivative is accumulated in factored form (e.g. the Gaussian keeps
 // sum w f (x_j - u_j)^2 and sum w f (x_j - u_j) per axis) and scaled once.
+//
+// Corner class.  Every family's node contribution is phi(s(x)) psi_j(x_j):
+// phi a function of the node's argument s (a left-to-right chain of
+// per-coordinate terms, as in the rule kernel) and psi_j a function of x_j
+// alone.  A corner's x_j is c_j + l5 h_j or c_j - l5 h_j, so the corner sum
+// of phi psi_j is psi_j(+) Phi_j^+ + psi_j(-) Phi_j^-, with Phi_j^+- the sums
+// of phi over the corners on either side of axis j.  The corners are swept
+// as a binary prefix tree over the per-coordinate terms (the last levels
+// unrolled, the leading axes' sign patterns looped over), and each tree node
+// adds its subtree's phi sum to Phi of its axis and side.
 #include "gm_adjoint.hpp"
 
 namespace gm {
@@ -129,7 +139,7 @@ __device__ __forceinline__ void adj_finish(const DevParams& P, double vol, const
 
 // Visit every node of region (c, h) in the rule's class order, calling
 // fn(class_weight_index, x).
-template <int D, typename Fn>
+template <int D, bool CORNERS = true, typename Fn>
 __device__ __forceinline__ void visit_nodes(const RuleConsts& K, const double (&c)[D],
                                             const double (&h)[D], Fn&& fn) {
   double x[D];
@@ -161,6 +171,7 @@ __device__ __forceinline__ void visit_nodes(const RuleConsts& K, const double (&
       }
     }
   }
+  if constexpr (!CORNERS) return;
   double xp[D], xm[D];
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -222,6 +233,140 @@ __device__ __forceinline__ void visit_nodes9_extra(const RuleConsts& K, const do
   }
 }
 
+// b^E for a compile-time E >= 1 by binary powering (E <= 18 here: at most
+// five multiplications, a few ulp).
+template <int E>
+__device__ __forceinline__ double ipow(double b) {
+  double y = 1.0, p = b;
+  bool first = true;
+#pragma unroll
+  for (int e = E; e > 0; e >>= 1) {
+    if (e & 1) {
+      y = first ? p : y * p;
+      first = false;
+    }
+    if (e > 1) p = p * p;
+  }
+  return y;
+}
+
+// Per-family split of a node's contribution into phi(s) and psi_j(x_j)
+// (the same quantities adj_node accumulates, without the class weight).
+template <int FAM>
+struct AdjSplit {
+  // the empty chain: comb(kEmpty, t) == t exactly
+  static constexpr double kEmpty = (FAM == kProductPeak) ? 1.0 : 0.0;
+  // per-coordinate term of the argument and its combination
+  __device__ static __forceinline__ double term(const DevParams& P, int j, double x) {
+    if constexpr (FAM == kOsc || FAM == kCornerPeak) {
+      return P.a[j] * x;
+    } else if constexpr (FAM == kProductPeak) {
+      const double t = x - P.u[j];
+      return 1.0 / (P.inv_a2[j] + t * t);
+    } else if constexpr (FAM == kGaussian) {
+      const double t = P.a[j] * (x - P.u[j]);
+      return t * t;
+    } else if constexpr (FAM == kC0) {
+      return P.a[j] * fabs(x - P.u[j]);
+    } else {
+      return (x > P.u[j]) ? -__builtin_inf() : P.a[j] * x;
+    }
+  }
+  __device__ static __forceinline__ double comb(double s, double t) {
+    if constexpr (FAM == kProductPeak) return s * t;
+    else return s + t;
+  }
+  template <int D>
+  __device__ static __forceinline__ double phi(const DevParams& P, double s) {
+    if constexpr (FAM == kOsc) return sin(P.c0 + s);
+    else if constexpr (FAM == kProductPeak) return s;
+    else if constexpr (FAM == kCornerPeak) return 1.0 / ipow<D + 2>(1.0 + s);
+    else if constexpr (FAM == kGaussian || FAM == kC0) return exp(-s);
+    else return exp(s);  // the discontinuous family: exp(-inf) = 0 outside its box
+  }
+  // add w (psi(+) Phi^+ + psi(-) Phi^-) for axis j into the factored sums
+  template <int D>
+  __device__ static __forceinline__ void add_axis(const DevParams& P, int j, double xp, double xm,
+                                                  double wp, double wm, double (&acc)[2 * D]) {
+    if constexpr (FAM == kOsc || FAM == kCornerPeak || FAM == kDiscontinuous) {
+      acc[j] = fma(wp, xp, fma(wm, xm, acc[j]));
+    } else if constexpr (FAM == kProductPeak) {
+      const double tp = xp - P.u[j], tm = xm - P.u[j];
+      const double rp = wp / (P.inv_a2[j] + tp * tp), rm = wm / (P.inv_a2[j] + tm * tm);
+      acc[j] += rp + rm;
+      acc[D + j] = fma(rp, tp, fma(rm, tm, acc[D + j]));
+    } else if constexpr (FAM == kGaussian) {
+      const double tp = xp - P.u[j], tm = xm - P.u[j];
+      acc[j] = fma(wp * tp, tp, fma(wm * tm, tm, acc[j]));
+      acc[D + j] = fma(wp, tp, fma(wm, tm, acc[D + j]));
+    } else {
+      const double tp = xp - P.u[j], tm = xm - P.u[j];
+      acc[j] = fma(wp, fabs(tp), fma(wm, fabs(tm), acc[j]));
+      const double sp = (tp > 0.0) ? wp : ((tp < 0.0) ? -wp : 0.0);
+      const double sm = (tm > 0.0) ? wm : ((tm < 0.0) ? -wm : 0.0);
+      acc[D + j] += sp + sm;
+    }
+  }
+};
+
+// Unrolled subtree over axes J .. D-1 below the prefix s: returns its phi
+// sum and adds each level's two halves to Phi^+ / Phi^- of that axis.
+template <int D, int FAM, int J>
+__device__ __forceinline__ double adj_corner_tree(const DevParams& P, double s,
+                                                  const double (&tp)[D], const double (&tm)[D],
+                                                  double (&fp)[D], double (&fm_)[D]) {
+  using S = AdjSplit<FAM>;
+  if constexpr (J == D) {
+    return S::template phi<D>(P, s);
+  } else {
+    const double a = adj_corner_tree<D, FAM, J + 1>(P, S::comb(s, tp[J]), tp, tm, fp, fm_);
+    const double b = adj_corner_tree<D, FAM, J + 1>(P, S::comb(s, tm[J]), tp, tm, fp, fm_);
+    fp[J] += a;
+    fm_[J] += b;
+    return a + b;
+  }
+}
+
+// The corner class (weight w) of region (c, h) added into acc.
+template <int D, int FAM>
+__device__ __forceinline__ void adj_corners(const DevParams& P, const RuleConsts& K, double w,
+                                            const double (&c)[D], const double (&h)[D],
+                                            double (&acc)[2 * D]) {
+  using S = AdjSplit<FAM>;
+  constexpr int U = D < 4 ? D : 4;  // unrolled levels
+  constexpr int H = D - U;          // looped leading axes
+  double xp[D], xm[D], tp[D], tm[D], fp[D], fm_[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    xp[j] = fma(K.lam5, h[j], c[j]);
+    xm[j] = fma(-K.lam5, h[j], c[j]);
+    tp[j] = S::term(P, j, xp[j]);
+    tm[j] = S::term(P, j, xm[j]);
+    fp[j] = 0.0;
+    fm_[j] = 0.0;
+  }
+  for (uint32_t hb = 0; hb < (1u << H); ++hb) {
+    double sum;
+    if constexpr (H == 0) {
+      sum = adj_corner_tree<D, FAM, 0>(P, S::kEmpty, tp, tm, fp, fm_);
+    } else {
+      // bit k of hb: the minus side on axis k (the corner order of the rule)
+      double s = ((hb & 1u) ? tm[0] : tp[0]);
+#pragma unroll
+      for (int k = 1; k < H; ++k) s = S::comb(s, ((hb >> k) & 1u) ? tm[k] : tp[k]);
+      sum = adj_corner_tree<D, FAM, H>(P, s, tp, tm, fp, fm_);
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        if ((hb >> k) & 1u) fm_[k] += sum;
+        else fp[k] += sum;
+      }
+    }
+    if constexpr (FAM == kOsc) acc[D] = fma(w, sum, acc[D]);
+  }
+#pragma unroll
+  for (int j = 0; j < D; ++j) S::template add_axis<D>(P, j, xp[j], xm[j], w * fp[j], w * fm_[j], acc);
+}
+
 template <int D, int FAM, bool R9>
 __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(AdjArgs A) {
   dd tot[2 * D];
@@ -236,16 +381,18 @@ __global__ __launch_bounds__(kAdjBlock) void adjoint_kernel(AdjArgs A) {
 #pragma unroll
     for (int j = 0; j < 2 * D; ++j) acc[j] = 0.0;
     if constexpr (R9) {
-      visit_nodes<D>(A.K, c, h, [&](int cls, const double (&x)[D]) {
+      visit_nodes<D, false>(A.K, c, h, [&](int cls, const double (&x)[D]) {
         adj_node<D, FAM>(A.P, x, A.K.w9[cls], acc);
       });
+      adj_corners<D, FAM>(A.P, A.K, A.K.w9[4], c, h, acc);
       visit_nodes9_extra<D>(A.K, c, h, [&](int cls, const double (&x)[D]) {
         adj_node<D, FAM>(A.P, x, A.K.w9[cls], acc);
       });
     } else {
-      visit_nodes<D>(A.K, c, h, [&](int cls, const double (&x)[D]) {
+      visit_nodes<D, false>(A.K, c, h, [&](int cls, const double (&x)[D]) {
         adj_node<D, FAM>(A.P, x, A.K.w[cls], acc);
       });
+      adj_corners<D, FAM>(A.P, A.K, A.K.w[4], c, h, acc);
     }
     double g[2 * D];
     adj_finish<D, FAM>(A.P, vol, acc, g);
