@@ -33,6 +33,22 @@ def test_grad_matches_oracle(fam, d):
     assert np.abs(g - ref["grad"]).max() <= 1e-12 * scale, (g, ref["grad"])
 
 
+@pytest.mark.parametrize("fam", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("d,tau", [(7, 1e-3), (10, 1e-3), (13, 1e-2)])
+def test_grad_matches_oracle_higher_dimensions(fam, d, tau):
+    """The adjoint's corner sweep loops over the leading axes' sign patterns
+    from d = 5 on (d - 4 of them); these dimensions exercise 3, 6 and 9 looped
+    axes against the oracle's node-by-node derivative sums."""
+    p = W.family_params(fam, d, seed=900 + 10 * fam + d)
+    print(f"case grad fam={fam} d={d} tau={tau}", flush=True)
+    I, E, g, st = gm.integrate_grad(fam, p, *W.unit_box(d), tau)
+    ref = O.integrate_grad(fam, p, *W.unit_box(d), tau)
+    assert st == ref["status"]
+    assert abs(I - ref["I"]) <= I_TOL * abs(ref["I"]) + 1e-300
+    scale = grad_scale(ref)
+    assert np.abs(g - ref["grad"]).max() <= 1e-12 * scale, (g, ref["grad"])
+
+
 def test_grad_gaussian_closed_form_and_fixed_tree_fd():
     d = 4
     rng = np.random.default_rng(44)
