@@ -7,16 +7,19 @@ Gaussian, C0, discontinuous) on [0,1]^8, each at rel_tol 1e-3, 1e-5 and
 1e-7, FP64, up to 2^24 active regions.  One step = the 18 integrals
 (every iteration runs rule, reduction, classify, scan, split/compaction).
 
-Also reported on the same JSON line:
-  roofline      the rule kernel (dominant) against the FP64 vector peak:
-                algorithmic FP64 FLOPs (evals x FLOPs per evaluation of the
-                family as implemented) / rule-kernel device time measured
-                with HIP events on the launch stream;
-  cpu_baseline  the serial CPU oracle on a bounded sample of the workload;
-  cases         per-integral time-to-tolerance, evals, regions, status;
-  batch, grad   the batched and gradient modes against one-call-per-integral.
+Output: one JSON line per detail section ({"detail": name, "data": ...}:
+per-integral cases, batch, grad, config3, gauss_kronrod, prune, degree9),
+then the compact headline as the LAST line (well under 4 KB), holding
+  roofline          the rule kernel (dominant) against the FP64 vector peak:
+                    algorithmic FP64 FLOPs (evals x FLOPs per evaluation of
+                    the family as implemented) / rule-kernel device time
+                    measured with HIP events on the launch stream;
+  split_compaction  classify + scan + scatter against the HBM peak;
+  cpu_baseline      the CPU oracle on a bounded sample of the workload;
+  batch, grad, ...  one-number summaries of the modes against
+                    one-call-per-integral.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--detail-out F]
 """
 from __future__ import annotations
 
@@ -35,6 +38,8 @@ sys.path.insert(0, ROOT)
 
 # MI355X published FP64 vector peak (256 CUs x 128 FP64 FLOP/clk x 2.4 GHz).
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# MI355X published HBM3E bandwidth.
+HBM_PEAK_GBPS = 8000.0
 
 # FP64 FLOPs per integrand evaluation as the rule kernel implements it:
 # counted from the compiled corner-sweep loop of the one-lane-per-region rule
@@ -66,7 +71,13 @@ def parse():
     ap.add_argument("--taus", default="1e-3,1e-5,1e-7")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the CPU-oracle sample")
-    ap.add_argument("--grad-tau", type=float, default=1e-6)
+    ap.add_argument("--grad-tau", type=float, default=1e-8,
+                    help="tolerance of the gradient workload (stated at 1e-8)")
+    ap.add_argument("--grad-rule", type=int, default=2, choices=(0, 2),
+                    help="rule of the gradient workload at --grad-tau: 2 degree 9 (default; the "
+                         "degree-7 rule needs far more than one GPU's store at 1e-8), 0 degree 7")
+    ap.add_argument("--detail-out", default=None,
+                    help="also write the full result (every case and mode) to this JSON file")
     ap.add_argument("--grad-log2cap", type=int, default=27)
     ap.add_argument("--config3-log2cap", type=int, default=27)
     ap.add_argument("--rule", type=int, default=0, choices=(0, 2),
@@ -153,9 +164,9 @@ def cpu_baseline(budget_s: float):
         pass_s = t_pass
         passes += 1
     return {"value": evals / secs, "unit": "integrand evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} pass(es) over {len(names)} full oracle runs of the d=8 workload at "
-                      f"rel_tol 1e-3/1e-5 ({', '.join(names)}); {evals} evals in {secs:.1f} s, "
-                      f"serial C, 1 thread"}
+            "sample": f"{passes} pass(es) over the {len(names)} full oracle runs of the d=8 "
+                      f"workload at rel_tol 1e-3/1e-5 (6 families x 2); {evals} evals in "
+                      f"{secs:.1f} s, serial C, 1 thread"}
 
 
 def bench_batch(gm, W, closed_forms):
@@ -380,10 +391,11 @@ def bench_prune(gm, W, closed_forms):
     return out
 
 
-def bench_grad(gm, W, closed_forms, tau: float, cap: int):
-    """C5 gradient (d = 8 Gaussian, 16 parameters): one gm_integrate_grad call
-    against 1 + 32 gm_integrate calls (the estimate plus central differences
-    h = 1e-6 of full adaptive runs), both compared with the erf closed form."""
+def bench_grad(gm, W, closed_forms, tau: float, cap: int, rule: int, fd: bool = True):
+    """The gradient workload (d = 8 Gaussian, 16 parameters): one
+    gm_integrate_grad call against 1 + 32 gm_integrate calls (the estimate plus
+    central differences h = 1e-6 of full adaptive runs), both with the same
+    rule and tolerance, compared with the erf closed form."""
     import numpy as np
     c = W.config5()
     p = c["params"]
@@ -391,41 +403,40 @@ def bench_grad(gm, W, closed_forms, tau: float, cap: int):
     a, u = p[:d], p[d:]
     want = np.array([float(x) for x in closed_forms.gaussian_grad(a, u)])
     exact = float(closed_forms.gaussian(a, u))
-    gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)  # warm-up
-    t0 = time.perf_counter()
-    I, E, g, st = gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
-    tg = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    I0 = gm.integrate(4, p, c["lo"], c["hi"], tau, 1e-16, cap)[0]
-    fd = np.zeros(2 * d)
-    for k in range(2 * d):
-        pp, pm = p.copy(), p.copy()
-        pp[k] += 1e-6
-        pm[k] -= 1e-6
-        fd[k] = (gm.integrate(4, pp, c["lo"], c["hi"], tau, 1e-16, cap)[0] -
-                 gm.integrate(4, pm, c["lo"], c["hi"], tau, 1e-16, cap)[0]) / 2e-6
-    tf = time.perf_counter() - t0
     scale = np.abs(want).max()
-    # the same gradient with the degree-9 rule (forward tree and adjoint)
-    gm.set_option("rule", 2)
+    gm.set_option("rule", rule)
     try:
-        gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
+        gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)  # warm-up
         t0 = time.perf_counter()
-        I9, E9, g9, st9 = gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
-        t9 = time.perf_counter() - t0
+        I, E, g, st = gm.integrate_grad(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
+        tg = time.perf_counter() - t0
+        s = gm.last_stats()
+        out = {"d": d, "rel_tol": tau, "rule": "degree9" if rule == 2 else "degree7",
+               "max_regions": cap, "status": st, "grad_s": tg, "regions": s["regions_evaluated"],
+               "integral_rel_err": abs(I - exact) / exact, "E_over_I": E / abs(I),
+               "grad_max_err_rel_to_max": float(np.abs(g - want).max() / scale)}
+        if fd:
+            t0 = time.perf_counter()
+            gm.integrate(4, p, c["lo"], c["hi"], tau, 1e-16, cap)
+            fdg = np.zeros(2 * d)
+            fst = []
+            for k in range(2 * d):
+                pp, pm = p.copy(), p.copy()
+                pp[k] += 1e-6
+                pm[k] -= 1e-6
+                ip, _, sp = gm.integrate(4, pp, c["lo"], c["hi"], tau, 1e-16, cap)
+                im, _, sm = gm.integrate(4, pm, c["lo"], c["hi"], tau, 1e-16, cap)
+                fdg[k] = (ip - im) / 2e-6
+                fst += [sp, sm]
+            tf = time.perf_counter() - t0
+            out.update({"fd_s": tf, "speedup": tf / tg, "fd_all_ok": all(x == 0 for x in fst),
+                        "fd_max_err_rel_to_max": float(np.abs(fdg - want).max() / scale)})
     finally:
         gm.set_option("rule", 0)
-    return {"d": d, "rel_tol": tau, "max_regions": cap, "status": st,
-            "grad_s": tg, "fd_s": tf, "speedup": tf / tg,
-            "integral_rel_err": abs(I - exact) / exact,
-            "grad_max_err_rel_to_max": float(np.abs(g - want).max() / scale),
-            "fd_max_err_rel_to_max": float(np.abs(fd - want).max() / scale),
-            "degree9": {"status": st9, "grad_s": t9, "speedup_vs_degree7_grad": tg / t9,
-                        "integral_rel_err": abs(I9 - exact) / exact,
-                        "grad_max_err_rel_to_max": float(np.abs(g9 - want).max() / scale)}}
+    return out
 
 
-def run_only(gm, W, mode: str, grad_tau: float, grad_cap: int):
+def run_only(gm, W, mode: str, grad_tau: float, grad_cap: int, grad_rule: int):
     """One mode by itself, for a kernel trace that holds nothing else: the
     4096-integral batch (one warm-up and one timed gm_integrate_batch call,
     as in the batch section) or the d = 8 Gaussian gradient (one warm-up and
@@ -447,13 +458,127 @@ def run_only(gm, W, mode: str, grad_tau: float, grad_cap: int):
                 "evals": gm.last_stats()["evals"],
                 "status_counts": {str(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}}
     c = W.config5()
-    gm.integrate_grad(4, c["params"], c["lo"], c["hi"], grad_tau, 1e-16, grad_cap)
-    t0 = time.perf_counter()
-    I, E, g, st = gm.integrate_grad(4, c["params"], c["lo"], c["hi"], grad_tau, 1e-16, grad_cap)
-    dt = time.perf_counter() - t0
-    s = gm.last_stats()
-    return {"mode": "grad", "d": 8, "rel_tol": grad_tau, "seconds": dt, "status": st,
-            "evals": s["evals"], "regions": s["regions_evaluated"]}
+    gm.set_option("rule", grad_rule)
+    try:
+        gm.integrate_grad(4, c["params"], c["lo"], c["hi"], grad_tau, 1e-16, grad_cap)
+        t0 = time.perf_counter()
+        I, E, g, st = gm.integrate_grad(4, c["params"], c["lo"], c["hi"], grad_tau, 1e-16, grad_cap)
+        dt = time.perf_counter() - t0
+        s = gm.last_stats()
+    finally:
+        gm.set_option("rule", 0)
+    return {"mode": "grad", "d": 8, "rel_tol": grad_tau, "rule": grad_rule, "seconds": dt,
+            "status": st, "evals": s["evals"], "regions": s["regions_evaluated"]}
+
+
+def split_compaction(gm, cases):
+    """HBM rate of classify + split/compaction (scan and scatter) over one pass
+    of the suite, timed per phase with HIP events on the launch stream
+    (option timing = 2; a pass of its own, outside the timed steps).
+    Algorithmic bytes: classify reads err, the level (one byte per region: two
+    children share their parent's) and the axis byte and writes the flag
+    (11 B per region) and reads Q of every retired region (8 B); the scatter
+    reads the flag and the axis byte (2 B per region) and, per kept region,
+    reads its parent record and writes its own (2 x (16d + 3) B)."""
+    gm.set_option("timing", 2)
+    try:
+        res = []
+        for c in cases:
+            gm.integrate(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"], c["abs_tol"],
+                         c["max_regions"])
+            res.append((c, gm.last_stats()))
+    finally:
+        gm.set_option("timing", 0)
+    by = 0.0
+    ms = 0.0
+    kept_total = 0
+    for c, s in res:
+        d = len(c["lo"])
+        n0 = 1 << (d * (12 // d))
+        kept = (s["regions_evaluated"] - n0) // 2  # every split's two children were evaluated
+        kept_total += kept
+        by += s["regions_evaluated"] * 13 + s["finished"] * 8 + kept * 2 * (16 * d + 3)
+        ms += s["classify_ms"] + s["split_ms"]
+    return {"algorithmic_bytes": by, "kept_regions": kept_total, "device_ms": ms,
+            "achieved_GBps": by / (ms * 1e-3) / 1e9, "peak_GBps": HBM_PEAK_GBPS,
+            "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+
+
+def _sig(x, n=4):
+    """Round a float to n significant digits for the compact line."""
+    if x is None or isinstance(x, (bool, int, str)):
+        return x
+    x = float(x)
+    if x == 0.0 or x != x or x in (float("inf"), float("-inf")):
+        return x
+    return float(f"{x:.{n - 1}e}")
+
+
+def headline(full: dict) -> dict:
+    """The compact last line (well under 4 KB): the contract fields, the
+    roofline and CPU-baseline objects, and one-number summaries of every
+    other section (their full detail is printed on the lines before)."""
+    S = _sig
+    h = {k: full[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                              "higher_is_better", "scaling", "vs_baseline", "dtype", "data",
+                              "config")}
+    h["value"] = S(h["value"], 6)
+    h["ms_per_step"] = S(h["ms_per_step"], 6)
+    h["regions_per_s"] = S(full["regions_per_s"])
+    cases = full.get("cases", [])
+    ttt = {}
+    for c in cases:
+        key = c["name"].rsplit("_tau", 1)[-1]
+        ttt[key] = ttt.get(key, 0.0) + c["seconds"] * 1e3
+    h["time_to_tolerance_ms_by_rel_tol"] = {k: S(v) for k, v in ttt.items()}
+    h["status_counts"] = {}
+    for c in cases:
+        h["status_counts"][str(c["status"])] = h["status_counts"].get(str(c["status"]), 0) + 1
+    if full.get("flags"):
+        h["flags"] = full["flags"]
+    r = full["roofline"]
+    h["roofline"] = {k: v for k, v in r.items()
+                     if k in ("bound", "kernel", "achieved", "peak", "unit", "frac", "traffic",
+                              "algorithmic_bytes_per_launch", "rule_avg_launch_ms",
+                              "rule_evals_per_s", "flops_per_eval")}
+    if "split_compaction" in full:
+        sc = full["split_compaction"]
+        h["split_compaction"] = {"bound": "hbm", "achieved": S(sc["achieved_GBps"]),
+                                 "peak": sc["peak_GBps"], "unit": "GB/s", "frac": S(sc["frac"])}
+    if "cpu_baseline" in full:
+        cb = full["cpu_baseline"]
+        h["cpu_baseline"] = {k: (S(v) if isinstance(v, float) else v) for k, v in cb.items()}
+    if "batch" in full:
+        b = full["batch"]
+        h["batch"] = {"integrals": b["integrals"], "speedup_vs_single_calls": S(b["speedup"]),
+                      "integrals_per_s": S(b["batch_integrals_per_s"]),
+                      "single_integrals_per_s": S(b["single_integrals_per_s"]),
+                      "all_ok": b["status_counts_batch"] == {"0": b["integrals"]},
+                      "max_rel_err": S(b["max_rel_err_vs_closed_form_every_16th"], 2)}
+        if "degree9" in b:
+            h["batch"]["degree9_integrals_per_s"] = S(b["degree9"]["batch_integrals_per_s"])
+    if "grad" in full:
+        g = full["grad"]
+        h["grad"] = {k: (S(v, 3) if isinstance(v, float) else v) for k, v in g.items()
+                     if k in ("rel_tol", "rule", "status", "speedup", "grad_s",
+                              "grad_max_err_rel_to_max", "fd_max_err_rel_to_max")}
+    if "config3" in full:
+        h["config3"] = {c["name"]: {"status": c["status"], "s": S(c["seconds"], 3),
+                                    "regions": c["regions"], "max_active": c["max_active"],
+                                    "rule_evals_per_s": S(c["rule_evals_per_s"], 3),
+                                    "rel_err": S(c["rel_err_vs_closed_form"], 2)}
+                        for c in full["config3"]}
+    if "degree9" in full:
+        t = full["degree9"]["totals"]
+        h["degree9_suite"] = {k: {"s": S(v["seconds"], 3), "evals": v["evals"]}
+                              for k, v in t.items()}
+    # stay far inside the driver's stdout tail: drop the least important
+    # summaries first if a run ever produced an unusually long line
+    for k in ("degree9_suite", "config3", "flags"):
+        if len(json.dumps(h)) <= 3800:
+            break
+        h.pop(k, None)
+    return h
 
 
 def main():
@@ -469,7 +594,8 @@ def main():
     from paper_2511_01573_amd import gm, workloads as W
 
     if args.only:
-        print(json.dumps(run_only(gm, W, args.only, args.grad_tau, 1 << args.grad_log2cap)))
+        print(json.dumps(run_only(gm, W, args.only, args.grad_tau, 1 << args.grad_log2cap,
+                                  args.grad_rule)))
         return
     taus = tuple(float(x) for x in args.taus.split(","))
     cases = W.config2(taus=taus)
@@ -495,7 +621,24 @@ def main():
     flops = sum(c["evals"] * FLOPS_PER_EVAL[c["family"]] for st in steps for c in st)
     launches = sum(c["rule_launches"] for st in steps for c in st)
     achieved = flops / rule_s / 1e12 if args.rule == 0 else None
+    # algorithmic HBM bytes per rule launch: per region half of the parent
+    # record two children share (8d + 1 B) read, Q, err and the axis byte (17 B)
+    # written
+    d = 8
+    alg_bytes = regions / launches * (8 * d + 1 + 17)
     last = steps[-1]
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import closed_forms
+    flags = []
+    for c, r in zip(cases, last):
+        ex = float(closed_forms.exact(c["family"], c["params"][:d], c["params"][d:]))
+        rel = abs(r["I"] - ex) / abs(ex)
+        r["rel_err_vs_closed_form"] = rel
+        if r["status"] != 0:
+            flags.append(f"{r['name']}: status {r['status']}, time to capacity")
+        elif rel > 10 * c["rel_tol"]:
+            flags.append(f"{r['name']}: E/I {r['E'] / abs(r['I']):.1e}, {rel:.1e} off the "
+                         "closed form (jump unseen by the estimate)")
     out = {
         "metric": "integrand evals/s (d=8 six-family Genz suite, rel_tol 1e-3/1e-5/1e-7)"
                   + (" with the degree-9 rule" if args.rule else ""),
@@ -518,24 +661,37 @@ def main():
                      "frac": achieved / FP64_VECTOR_PEAK_TFLOPS if achieved else None,
                      "traffic": measured_traffic() if args.rule == 0 else None,
                      "traffic_unit": "HBM bytes per launch",
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "flops_per_eval": flops / evals,
                      "rule_kernel_s": rule_s, "rule_launches": launches,
                      "rule_avg_launch_ms": rule_s / launches * 1e3,
                      "rule_evals_per_s": evals / rule_s},
         "cases": [{k: c[k] for k in ("name", "status", "seconds", "evals", "regions", "iterations",
-                                     "I", "E")} for c in last],
+                                     "I", "E", "rel_err_vs_closed_form")} for c in last],
+        "flags": flags,
     }
+    if args.rule == 0:
+        out["split_compaction"] = split_compaction(gm, cases)
     if not args.no_modes:
-        sys.path.insert(0, os.path.join(ROOT, "tests"))
-        import closed_forms
         out["batch"] = bench_batch(gm, W, closed_forms)
-        out["grad"] = bench_grad(gm, W, closed_forms, args.grad_tau, 1 << args.grad_log2cap)
+        out["grad"] = bench_grad(gm, W, closed_forms, args.grad_tau, 1 << args.grad_log2cap,
+                                 args.grad_rule)
+        out["grad_degree7_1e-6"] = bench_grad(gm, W, closed_forms, 1e-6, 1 << args.grad_log2cap,
+                                              0, fd=False)
         out["config3"] = bench_config3(gm, W, closed_forms, args.config3_log2cap)
         out["gauss_kronrod"] = bench_gk(gm, W, closed_forms)
         out["prune"] = bench_prune(gm, W, closed_forms)
         out["degree9"] = bench_degree9(gm, W, closed_forms, args.config3_log2cap)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    print(json.dumps(out))
+    # detail first (one line per section), the compact headline last
+    for k, v in out.items():
+        if isinstance(v, (list, dict)) and k not in ("config", "roofline", "cpu_baseline"):
+            print(json.dumps({"detail": k, "data": v}))
+    if args.detail_out:
+        with open(args.detail_out, "w") as fh:
+            json.dump(out, fh, indent=1)
+    print(json.dumps(headline(out)), flush=True)
 
 
 if __name__ == "__main__":

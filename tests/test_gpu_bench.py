@@ -1,6 +1,7 @@
-"""The benchmark's JSON line on a short run: one line with the metric, the
-roofline object of the rule kernel (bound, achieved, peak, unit, frac,
-traffic) and the CPU-oracle baseline (value, unit, cores, kind, sample)."""
+"""The benchmark's JSON output on a short run: detail lines, then the compact
+headline as the last line, with the metric, the roofline object of the rule
+kernel (bound, achieved, peak, unit, frac, traffic) and the CPU-oracle
+baseline (value, unit, cores, kind, sample)."""
 from __future__ import annotations
 
 import json
@@ -22,8 +23,11 @@ def test_bench_line_has_the_contract_fields():
                        capture_output=True, text=True, timeout=110)
     assert p.returncode == 0, p.stderr[-2000:]
     lines = [l for l in p.stdout.splitlines() if l.strip()]
-    assert len(lines) == 1
-    out = json.loads(lines[0])
+    # detail sections first, the compact headline last
+    assert len(lines[-1].encode()) < 4096
+    for l in lines[:-1]:
+        assert "detail" in json.loads(l)
+    out = json.loads(lines[-1])
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
               "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config"):
         assert k in out, k
