@@ -103,6 +103,27 @@ def c0(a, u):
     return p
 
 
+def c0_grad(a, u):
+    """d/da_j and d/du_j of the C0 closed form (2d mpf): with the factor
+    F_j = (2 - e^{-a u} - e^{-a(1-u)})/a,
+      dF/da = (u e^{-a u} + (1-u) e^{-a(1-u)})/a - F/a,
+      dF/du = e^{-a u} - e^{-a(1-u)},
+    and dI/dtheta_j = I / F_j * dF_j/dtheta_j."""
+    d = len(a)
+    fs, da, du = [], [], []
+    for x, y in zip(a, u):
+        x, y = _mpf(x), _mpf(y)
+        e0, e1 = mp.exp(-x * y), mp.exp(-x * (1 - y))
+        F = (2 - e0 - e1) / x
+        fs.append(F)
+        da.append((y * e0 + (1 - y) * e1) / x - F / x)
+        du.append(e0 - e1)
+    I = mp.mpf(1)
+    for F in fs:
+        I *= F
+    return [I / fs[j] * da[j] for j in range(d)] + [I / fs[j] * du[j] for j in range(d)]
+
+
 def discontinuous(a, u):
     """f = 0 if x_j > u_j for ANY j, else exp(sum a x): prod (e^{a b} - 1)/a, b = clip(u, 0, 1)."""
     p = mp.mpf(1)

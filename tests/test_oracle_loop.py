@@ -252,7 +252,9 @@ def test_gradient_fixed_tree_fd_all_families(fam):
     if fam == 6:
         fd[d:] = 0.0  # jump location: not a derivative of the fixed-tree sum
     if fam == 5:
-        # |x - u| kinks: nodes exactly at u make the one-sided FD differ; skip u
+        # the |x - u| kinks: a node within the step of u_j would make the
+        # difference quotient straddle the kink; the C0 u-partials are pinned
+        # on kinks placed at dyadic cell boundaries below
         fd[d:] = res["grad"][d:]
     scale = max(np.abs(fd).max(), 1e-300)
     assert np.abs(res["grad"] - fd).max() <= 1e-6 * scale, (res["grad"], fd)
@@ -292,3 +294,65 @@ def test_batch_shared_capacity_stops_all_running():
                                               3000, init_log2=4)
     assert st[0] == O.OK  # easy one converges before the budget is hit
     assert st[1] == O.MAX_REGIONS and rc == O.MAX_REGIONS
+
+
+def _min_node_distance(c, h, lam, axis, u):
+    """Smallest |x_axis - u| over every node of every leaf: the node
+    coordinates along an axis are c + s lam_k h (s = +-1, lam_k the
+    generator lengths, 0 for the centre)."""
+    best = np.inf
+    for l in set(float(x) for x in lam):
+        for s in (1.0, -1.0):
+            best = min(best, float(np.min(np.abs(c[:, axis] + s * l * h[:, axis] - u))))
+    return best
+
+
+@pytest.mark.parametrize("d,u", [(3, (0.25, 0.625, 0.375)), (4, (0.375, 0.75, 0.25, 0.875))])
+def test_c0_u_partials_fixed_tree_fd_and_closed_form(d, u):
+    """Pin of the C0 family's u-partials (df/du_j = a_j sign(x_j - u_j) f).
+    With u_j on a dyadic cell boundary, every region of the tree lies on one
+    side of each kink and every node stays at least (1 - lam3) h_j from it, so
+    the fixed-tree quadrature is smooth in u across the difference step: its
+    central differences (h = 1e-7) pin all 2d partials, and at a tight
+    tolerance the gradient matches the closed-form gradient of the integral."""
+    rng = np.random.default_rng(70 + d)
+    a = rng.uniform(1, 4, d)
+    u = np.array(u, dtype=float)
+    p = np.concatenate([a, u])
+    res = O.integrate_grad(O.C0, p, *unit(d), 1e-7, max_regions=1 << 21)
+    assert res["status"] == O.OK
+    c, h, lvl = res["leaves"]
+    lam = O.constants(d)[0]
+    step = 1e-7
+    for j in range(d):
+        assert _min_node_distance(c, h, lam, j, u[j]) > 20 * step
+    fd = np.zeros(2 * d)
+    for k in range(2 * d):
+        pp, pm = p.copy(), p.copy()
+        pp[k] += step
+        pm[k] -= step
+        qp, _ = O.quad_leaves(O.C0, pp, c, h, lvl, res["vol_omega"])
+        qm, _ = O.quad_leaves(O.C0, pm, c, h, lvl, res["vol_omega"])
+        fd[k] = (qp - qm) / (2 * step)
+    scale = np.abs(fd).max()
+    assert np.abs(res["grad"] - fd).max() <= 1e-6 * scale, (res["grad"], fd)
+    want = np.array([float(x) for x in cf.c0_grad(a, u)])
+    assert np.abs(res["grad"] - want).max() <= 1e-5 * np.abs(want).max(), (res["grad"], want)
+    # a sign or scale mistake in the u-partials is far outside both bounds
+    assert np.abs(want[d:]).min() > 1e-3 * np.abs(want).max()
+
+
+def test_c0_u_partial_closed_form_flips_sign_across_the_peak():
+    """The closed form the C0 pin uses: dI/du_j changes sign with u_j - 1/2
+    and vanishes at u_j = 1/2 (symmetric factor), checked against central
+    differences of the closed-form integral itself."""
+    a = [2.0, 3.0]
+    for uj, sgn in ((0.3, 1), (0.5, 0), (0.8, -1)):
+        u = [uj, 0.4]
+        g = cf.c0_grad(a, u)
+        fdv = (cf.c0(a, [uj + 1e-8, 0.4]) - cf.c0(a, [uj - 1e-8, 0.4])) / 2e-8
+        assert abs(float(g[2]) - float(fdv)) <= 1e-6 * abs(float(cf.c0(a, u)))
+        if sgn == 0:
+            assert abs(float(g[2])) < 1e-30
+        else:
+            assert np.sign(float(g[2])) == sgn
