@@ -136,10 +136,15 @@ int gm_eval_regions(int integrand_id, const double* params, int d, const double*
 
 /*
  * gm_set_workspace -- register a caller-owned DEVICE buffer (e.g. a torch
- * uint8 tensor) used for all device scratch instead of library allocations.
- * bytes == 0 (or ptr == NULL) returns to library-owned memory.  The caller
- * keeps the buffer alive while registered; the library never frees it.
- * Calls needing more than `bytes` return GM_ENOMEM.
+ * uint8 tensor) used for the region store and every other per-call device
+ * buffer of gm_integrate, gm_integrate_grad and gm_integrate_batch instead of
+ * library allocations (gm_workspace_bytes gives the size; the gradient
+ * mode's store of retired leaves, whose size is only known as the run goes,
+ * stays library-owned).  device_ptr must be 256-byte aligned (GM_EINVAL
+ * otherwise).  bytes == 0 (or ptr == NULL) returns to library-owned memory.
+ * The caller keeps the buffer alive while registered; the library never frees
+ * it and writes only its first `bytes` bytes.  A call needing more than
+ * `bytes` returns GM_ENOMEM before any device work, outputs untouched.
  */
 int gm_set_workspace(void* device_ptr, size_t bytes);
 
@@ -152,8 +157,17 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  * gm_set_option -- process-wide knobs.  Returns GM_OK or GM_EINVAL.
  *   "init_log2_regions"  L0, initial partition 2^(d*floor(L0/d)) cells (default 12, 0..30)
  *   "max_iters"          iteration budget (default 10000, >= 1)
- *   "graph_iters"        iterations per hipGraph replay, 0 = launch kernels
- *                        directly with a host check every iteration (default 0)
+ *   "graph_iters"        iterations enqueued per host read of the device status
+ *                        block.  gm_integrate: 0 (default) = automatic, 6 while
+ *                        the active set is below 2^16 regions, 3 below 2^20, 2
+ *                        above; k >= 1 = k iterations (at most 8); kernels are
+ *                        launched directly (no graph) and those queued past the
+ *                        end return at once.  gm_integrate_grad reads the status
+ *                        after every iteration whatever the value.
+ *                        gm_integrate_batch: k >= 1 = one iteration's kernels
+ *                        are captured k times into a hipGraph (kernel nodes
+ *                        only) that is replayed until every item has stopped;
+ *                        0 = direct launches and a host read every iteration
  *   "lanes_per_region"   0 = automatic, else 1..64 power of two (rule kernel mapping)
  *   "timing"             1 = record the rule kernel's device time with hipEvents on
  *                        the call's stream, 2 = every phase (default 0 = off)

@@ -1222,6 +1222,7 @@ int gm_set_workspace(void* device_ptr, size_t bytes) {
     g_ext_bytes = 0;
     return GM_OK;
   }
+  if (((uintptr_t)device_ptr & 255u) != 0) return GM_EINVAL;
   g_ext_ptr = device_ptr;
   g_ext_bytes = bytes;
   return GM_OK;

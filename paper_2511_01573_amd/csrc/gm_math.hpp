@@ -30,7 +30,7 @@
 #include <cstring>
 
 #ifndef GM_HD
-#if defined(__HIPCC__) || defined(__CUDACC__)
+#if defined(__HIPCC__)
 #define GM_HD __host__ __device__ __forceinline__
 #else
 #define GM_HD inline

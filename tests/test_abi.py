@@ -43,6 +43,16 @@ def test_status_strings_and_node_count():
         assert gm.num_nodes(d) == 2 ** d + 2 * d * d + 2 * d + 1
 
 
+def test_workspace_registration_checks_alignment():
+    """gm_set_workspace only records the buffer (no device access): a pointer
+    that is not 256-byte aligned is refused, an aligned one is accepted, and a
+    null pointer returns to library-owned memory."""
+    L = gm.lib()
+    assert L.gm_set_workspace(C.c_void_p(0x10010), 4096) == gm.EINVAL
+    assert L.gm_set_workspace(C.c_void_p(0x10000), 4096) == gm.OK
+    assert L.gm_set_workspace(None, 0) == gm.OK
+
+
 def test_workspace_bytes_scales_with_capacity():
     a = gm.workspace_bytes(8, 1 << 20)
     b = gm.workspace_bytes(8, 1 << 21)

@@ -136,3 +136,70 @@ def test_batch_4096_sampled_items():
         assert abs(err[i] - ref["E"]) <= 1e-13 * ref["escale"] + 1e-15 * abs(ref["E"]), (i, err[i], ref["E"])
         checked += 1
     assert checked >= 100
+
+
+def _batch_high_d_items(b, lo_tau, hi_tau, every):
+    """Items of dimension 8..10 with lo_tau <= rel_tol < hi_tau, every
+    `every`-th in item order."""
+    items = [i for i in range(len(b["families"]))
+             if b["ds"][i] >= 8 and lo_tau <= b["rel_tols"][i] < hi_tau]
+    return items[::every]
+
+
+def test_batch_4096_high_dimension_items_to_convergence():
+    """Batch items of dimension 8..10 (the batch-store rule kernels that take
+    most of the batch's time) replayed by the oracle as independent runs:
+    every second item with 1e-5 <= rel_tol < 1e-4 (they converge within 1..5
+    iterations; the tighter items are covered by the stopped runs below)."""
+    b = W.config4()
+    gm.set_option("graph_iters", 8)
+    try:
+        print("case batch 4096 cap 2^28 (high-d items)", flush=True)
+        rc, est, err, st = gm.integrate_batch(b["families"], b["params"], b["ds"], b["los"],
+                                              b["his"], b["rel_tols"], b["abs_tols"], 1 << 28)
+    finally:
+        gm.set_option("graph_iters", 0)
+    assert rc == gm.OK and (st == gm.OK).all()
+    items = _batch_high_d_items(b, 1e-5, 1e-4, 2)
+    assert len(items) >= 150
+    multi = 0
+    for i in items:
+        ref = O.integrate(b["families"][i], b["params"][i], b["los"][i], b["his"][i],
+                          b["rel_tols"][i], b["abs_tols"][i], 1 << 26)
+        assert ref["status"] == st[i] == gm.OK, (i, ref["status"], st[i])
+        assert abs(est[i] - ref["I"]) <= I_TOL * abs(ref["I"]), (i, est[i], ref["I"])
+        assert abs(err[i] - ref["E"]) <= 1e-13 * ref["escale"] + 1e-15 * abs(ref["E"]), (i, err[i], ref["E"])
+        multi += ref["iterations"] > 1
+    assert multi >= 15  # items that refined, not only the initial partition
+    assert {b["ds"][i] for i in items} == {8, 9, 10}
+
+
+@pytest.mark.parametrize("k,count", [(3, 32), (6, 24)])
+def test_batch_4096_high_dimension_items_stopped_after_k_iterations(k, count):
+    """The whole batch stopped after k lock-step iterations (option
+    max_iters, as the benchmark runs it: graph replay of 8 iterations, store of
+    2^28 regions): items of dimension 8..10 with rel_tol < 1e-5, spread over
+    the tolerance range, against independent oracle runs stopped after k
+    iterations (same status, I, E: the rule, reduction, classification and
+    splitting of every iteration up to k)."""
+    b = W.config4()
+    gm.set_option("graph_iters", 8)
+    gm.set_option("max_iters", k)
+    try:
+        print(f"case batch 4096 cap 2^28 max_iters={k}", flush=True)
+        rc, est, err, st = gm.integrate_batch(b["families"], b["params"], b["ds"], b["los"],
+                                              b["his"], b["rel_tols"], b["abs_tols"], 1 << 28)
+    finally:
+        gm.set_option("graph_iters", 0)
+        gm.set_option("max_iters", 10000)
+    tight = sorted(_batch_high_d_items(b, 0.0, 1e-5, 1), key=lambda i: b["rel_tols"][i])
+    items = tight[:: max(1, len(tight) // count)][:count]
+    stopped = 0
+    for i in items:
+        ref = O.integrate(b["families"][i], b["params"][i], b["los"][i], b["his"][i],
+                          b["rel_tols"][i], b["abs_tols"][i], 1 << 26, max_iters=k)
+        assert ref["status"] == st[i], (i, ref["status"], st[i])
+        assert abs(est[i] - ref["I"]) <= I_TOL * abs(ref["I"]), (i, est[i], ref["I"])
+        assert abs(err[i] - ref["E"]) <= 1e-13 * ref["escale"] + 1e-15 * abs(ref["E"]), (i, err[i], ref["E"])
+        stopped += st[i] == gm.MAX_ITERS
+    assert stopped >= 3  # items the stop actually cut short
