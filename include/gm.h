@@ -121,6 +121,29 @@ int gm_integrate_grad(int integrand_id, const double* params, int d, const doubl
                       double* out_est, double* out_err, double* out_grad, void* stream);
 
 /*
+ * gm_integrate_noalloc -- gm_integrate for callers that cannot allocate
+ * device or pinned memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, options, results
+ * and kernels as gm_integrate, but every device buffer of the run (region
+ * store, per-region outputs, tile counts, status block) is laid out in a
+ * fixed device array of 64 MiB that the library holds on each GPU it runs on
+ * until the process ends; the call makes no hipMalloc, hipFree, hipHostMalloc
+ * or other allocating call (the status block is read through a pinned host
+ * copy only if an earlier gm_integrate made one; option "timing" is ignored).
+ *   max_regions   as gm_integrate, and the run's buffers must fit the array:
+ *                 gm_workspace_bytes(d, max_regions, 0) <= 64 MiB (about
+ *                 2.3e5 regions at d = 8, 1.2e5 at d = 16), else GM_EINVAL
+ *                 before anything runs.
+ * The array is shared by every call on that GPU and keeps the last call's
+ * contents (each run writes its initial partition and status block before
+ * reading them).  Calls from one process are serialised by the library's
+ * mutex; calls that overlap on one GPU from several processes race.
+ */
+int gm_integrate_noalloc(int integrand_id, const double* params, int d, const double* lo,
+                         const double* hi, double rel_tol, double abs_tol, int64_t max_regions,
+                         double* out_est, double* out_err, void* stream);
+
+/*
  * gm_eval_regions -- the rule kernel alone on a caller-given region list
  * (Sec. 2: rule value, error estimate and split axis of each region), with
  * the rule and error model the options "rule" and "err_model" select.

@@ -471,6 +471,7 @@ struct LastRun {
   int split = 0;
   Layout lay;
   int buf = 0;
+  char* base = nullptr;  // device buffers of that run
 } g_last;
 
 int hip_fail(hipError_t e) {
@@ -538,6 +539,7 @@ int acquire_workspace(size_t bytes, char** base) {
     return GM_OK;
   }
   if (bytes > g_own_bytes) {
+    g_last.valid = false;  // the last run's buffers go away
     if (g_own_ptr) {
       GM_HIP(hipDeviceSynchronize());
       GM_HIP(hipFree(g_own_ptr));
@@ -817,20 +819,52 @@ static int leaf_reserve(int d, int64_t need, int64_t have, hipStream_t s) {
 
 // Pinned host copy of the status block: the host's status reads and the
 // initial write are direct DMA transfers instead of staged pageable copies.
-static Status* pinned_status() {
+// create = false returns the copy only if an earlier call made it.
+static Status* pinned_status(bool create = true) {
   static Status* p = nullptr;
-  if (!p && hipHostMalloc((void**)&p, sizeof(Status), hipHostMallocDefault) != hipSuccess) {
+  if (!p && create &&
+      hipHostMalloc((void**)&p, sizeof(Status), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     p = nullptr;
   }
   return p;
 }
 
+// Fixed device scratch of gm_integrate_noalloc (callers that cannot allocate):
+// a file-scope array each device holds until the process ends.  In host code
+// `scratch` names a host-side stand-in, never the device address: the address
+// is looked up once per device with hipGetSymbolAddress (that device current)
+// and only that pointer is handed to kernels and copies.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+static char* g_scratch_dev[kMaxDevices] = {};
+
+static int noalloc_scratch(char** out) {
+  int dev = 0;
+  GM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_hip_err = "device index beyond the no-allocation scratch table";
+    return GM_EHIP;
+  }
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    GM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255u) != 0) {
+      g_hip_err = "no-allocation scratch: unexpected device address";
+      return GM_EHIP;
+    }
+    g_scratch_dev[dev] = (char*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return GM_OK;
+}
+
 // One adaptive run on the device (gm_integrate and the forward pass of
 // gm_integrate_grad).  On return the status block holds the final state.
 int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,
                  double rel_tol, double abs_tol, int64_t max_regions, hipStream_t s,
-                 bool keep_leaves, RunResult* out) {
+                 bool keep_leaves, RunResult* out, char* fixed_base) {
   const auto t_start = std::chrono::steady_clock::now();
   std::memset(&g_stats, 0, sizeof g_stats);
   const int m = init_cells_log2(d);
@@ -838,10 +872,13 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   if (max_regions < n0) return GM_EINVAL;
   const int64_t cap = max_regions;
   const Layout lay = make_layout(d, cap);
-  char* base = nullptr;
-  int rc = acquire_workspace(lay.total, &base);
-  if (rc != GM_OK) return rc;
-  g_last.valid = false;
+  g_last.valid = false;  // (before the workspace may move)
+  char* base = fixed_base;
+  int rc = GM_OK;
+  if (!base) {
+    rc = acquire_workspace(lay.total, &base);
+    if (rc != GM_OK) return rc;
+  }
 
   RuleArgs ra;
   std::memset(&ra, 0, sizeof ra);
@@ -915,7 +952,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   hst.rel_tol = rel_tol;
   hst.abs_tol = abs_tol;
   hst.prune_on = g_opt.prune;
-  Status* const pin = pinned_status();
+  Status* const pin = pinned_status(fixed_base == nullptr);
   if (pin) {
     *pin = hst;
     GM_HIP(hipMemcpyAsync(st, pin, sizeof hst, hipMemcpyHostToDevice, s));
@@ -937,8 +974,9 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   // store grows on the host's side).
   constexpr int kMaxAhead = 8;
   hipEvent_t ev[kMaxAhead][5] = {};
-  const bool timing = g_opt.timing != 0;       // rule kernel only
-  const bool phases = g_opt.timing >= 2;       // every phase
+  // (events are created per run: not on the no-allocation path)
+  const bool timing = g_opt.timing != 0 && !fixed_base;  // rule kernel only
+  const bool phases = timing && g_opt.timing >= 2;       // every phase
   if (timing)
     for (auto& row : ev)
       for (auto& e : row) GM_HIP(hipEventCreate(&e));
@@ -1049,6 +1087,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
   g_stats.total_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   g_last.valid = true;
+  g_last.base = base;
   g_last.d = d;
   g_last.n = hst.n_active;
   g_last.npar = hst.n_par;
@@ -1086,6 +1125,26 @@ int gm_integrate(int integrand_id, const double* params, int d, const double* lo
   return rr.status;
 }
 
+int gm_integrate_noalloc(int integrand_id, const double* params, int d, const double* lo,
+                         const double* hi, double rel_tol, double abs_tol, int64_t max_regions,
+                         double* out_est, double* out_err, void* stream) {
+  int rc = validate(integrand_id, params, d, lo, hi, rel_tol, abs_tol);
+  if (rc != GM_OK) return rc;
+  if (!out_est || !out_err || max_regions < 1) return GM_EINVAL;
+  if (make_layout(d, max_regions).total > kNoallocScratchBytes) return GM_EINVAL;
+  std::lock_guard<std::mutex> lk(api_mutex());
+  char* base = nullptr;
+  rc = noalloc_scratch(&base);
+  if (rc != GM_OK) return rc;
+  RunResult rr;
+  rc = run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions,
+                    (hipStream_t)stream, false, &rr, base);
+  if (rc != GM_OK) return rc;
+  *out_est = rr.I;
+  *out_err = rr.E;
+  return rr.status;
+}
+
 int gm_eval_regions(int integrand_id, const double* params, int d, const double* lo,
                     const double* hi, int64_t n, const double* c, const double* h,
                     const int32_t* lvl, double* out_q, double* out_err, int32_t* out_axis,
@@ -1101,9 +1160,9 @@ int gm_eval_regions(int integrand_id, const double* params, int d, const double*
   const int64_t cap = n;
   const Layout lay = make_layout(d, cap);
   char* base = nullptr;
+  g_last.valid = false;  // (before the workspace may move)
   rc = acquire_workspace(lay.total, &base);
   if (rc != GM_OK) return rc;
-  g_last.valid = false;
   std::vector<double> cs((size_t)d * n), hs((size_t)d * n);
   std::vector<uint16_t> ls((size_t)n);
   for (int64_t r = 0; r < n; ++r) {
@@ -1149,7 +1208,7 @@ int64_t gm_last_active(int64_t offset, int64_t n, double* c, double* h, int32_t*
   std::lock_guard<std::mutex> lk(api_mutex());
   if (!g_last.valid) return 0;
   if (offset < 0) return GM_EINVAL;
-  char* base = g_ext_ptr ? (char*)g_ext_ptr : (char*)g_own_ptr;
+  char* base = g_last.base;
   const int64_t cnt = std::min<int64_t>(n, g_last.n - offset);
   const int d = g_last.d;
   const int b = g_last.buf;

@@ -70,9 +70,13 @@ RuleKernelFn gk_kernel(int d, int fam, bool batch);
 int64_t nodes_per_region(int d);
 bool mapping_allowed(int d, int log2l);
 int rule_grid(int log2l, int64_t n, int d);
+// fixed_base: when not null, the run's device buffers are laid out from it
+// (the no-allocation entry point's fixed scratch, already checked to be large
+// enough) and the run allocates nothing: no workspace, no pinned status copy
+// (an existing one is used), no timing events.
 int run_adaptive(int fam, const double* params, int d, const double* lo, const double* hi,
                  double rel_tol, double abs_tol, int64_t max_regions, hipStream_t s,
-                 bool keep_leaves, RunResult* out);
+                 bool keep_leaves, RunResult* out, char* fixed_base = nullptr);
 size_t batch_layout_bytes(int dmax, int64_t cap);
 
 // Process-wide lock serialising every C ABI call.

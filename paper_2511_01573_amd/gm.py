@@ -26,7 +26,7 @@ EINVAL, ENOMEM, EHIP = -1, -2, -3
 EXPORTED = [
     "gm_integrate", "gm_integrate_batch", "gm_integrate_grad", "gm_eval_regions",
     "gm_set_workspace", "gm_workspace_bytes", "gm_set_option", "gm_status_string",
-    "gm_last_stats", "gm_num_nodes", "gm_last_active", "gm_set_tile",
+    "gm_last_stats", "gm_num_nodes", "gm_last_active", "gm_set_tile", "gm_integrate_noalloc",
 ]
 
 
@@ -74,6 +74,8 @@ def lib():
         L.gm_integrate.restype = C.c_int
         L.gm_integrate.argtypes = [C.c_int, dp, C.c_int, dp, dp, C.c_double, C.c_double,
                                    C.c_int64, dp, dp, C.c_void_p]
+        L.gm_integrate_noalloc.restype = C.c_int
+        L.gm_integrate_noalloc.argtypes = L.gm_integrate.argtypes
         L.gm_integrate_batch.restype = C.c_int
         L.gm_integrate_batch.argtypes = [C.c_int, ip, dp, ip, dp, dp, dp, dp, C.c_int64, dp, dp,
                                          ip, C.c_void_p]
@@ -179,6 +181,23 @@ def integrate(family, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 2
     rc = lib().gm_integrate(family_id(family), pp, d, lp, hp, float(rel_tol), float(abs_tol),
                             int(max_regions), C.byref(est), C.byref(err),
                             C.c_void_p(_stream(stream)))
+    _check(rc)
+    return est.value, err.value, rc
+
+
+def integrate_noalloc(family, params, lo, hi, rel_tol, abs_tol=1e-16, max_regions=1 << 16,
+                      stream=None):
+    """gm_integrate_noalloc (no device allocation: the library's fixed 64 MiB
+    scratch); returns (estimate, error, status)."""
+    p, pp = _d(params)
+    lo, lp = _d(lo)
+    hi, hp = _d(hi)
+    d = lo.size
+    est = C.c_double()
+    err = C.c_double()
+    rc = lib().gm_integrate_noalloc(family_id(family), pp, d, lp, hp, float(rel_tol),
+                                    float(abs_tol), int(max_regions), C.byref(est), C.byref(err),
+                                    C.c_void_p(_stream(stream)))
     _check(rc)
     return est.value, err.value, rc
 

@@ -1,0 +1,88 @@
+"""gm_integrate_noalloc, the variant of gm_integrate for callers that cannot
+allocate: its run lives in the library's fixed device scratch.  Two calls in a
+row (the second on a smaller input) give exactly gm_integrate's results --
+estimate, error, status, iteration and region counts, and the last active
+set region by region -- sizes beyond the scratch are refused, and a call
+takes no device memory."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2511_01573_amd import gm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SCRATCH = 64 << 20
+
+
+def _cases():
+    d = 5
+    p5 = W.family_params(W.C0, d, seed=1905)
+    c1 = W.config1()
+    return [
+        # (family, params, lo, hi, rel_tol, max_regions)
+        (W.C0, p5, *W.unit_box(d), 1e-6, 1 << 17),
+        (c1["family"], c1["params"], c1["lo"], c1["hi"], c1["rel_tol"], c1["max_regions"]),
+    ]
+
+
+def _active(d):
+    n = gm.last_active_count()
+    return n, gm.last_active(d, 0, min(n, 4096)), gm.last_active(d, max(0, n - 512), 512)
+
+
+def test_noalloc_matches_gm_integrate_on_two_calls_in_a_row():
+    cases = _cases()
+    for fam, p, lo, hi, tau, cap in cases:
+        assert gm.workspace_bytes(len(lo), cap, 0) <= SCRATCH
+    got = []
+    for k, (fam, p, lo, hi, tau, cap) in enumerate(cases):
+        print(f"case noalloc call {k} fam={fam} d={len(lo)} cap={cap}", flush=True)
+        r = gm.integrate_noalloc(fam, p, lo, hi, tau, 1e-16, cap)
+        got.append((r, gm.last_stats(), _active(len(lo))))
+    for (fam, p, lo, hi, tau, cap), (r, s, act) in zip(cases, got):
+        ref = gm.integrate(fam, p, lo, hi, tau, 1e-16, cap)
+        rs = gm.last_stats()
+        ract = _active(len(lo))
+        assert r == ref, (r, ref)
+        assert r[2] == gm.OK
+        for key in ("iterations", "regions_evaluated", "max_active", "final_active", "finished"):
+            assert s[key] == rs[key], key
+        assert act[0] == ract[0]
+        for a, b in zip(act[1:], ract[1:]):
+            for key in ("c", "h", "lvl", "Q", "err", "axis"):
+                assert np.array_equal(a[key], b[key]), key
+
+
+def test_noalloc_refuses_a_store_beyond_the_scratch():
+    d = 8
+    p = W.family_params(W.GAUSSIAN, d, seed=3)
+    cap = 1 << 20
+    assert gm.workspace_bytes(d, cap, 0) > SCRATCH
+    with pytest.raises(gm.GMError) as ei:
+        gm.integrate_noalloc(W.GAUSSIAN, p, *W.unit_box(d), 1e-5, 1e-16, cap)
+    assert ei.value.code == gm.EINVAL
+
+
+def test_noalloc_takes_no_device_memory():
+    """A call whose region store (36 MiB at d = 8, 2^17 regions) would be a
+    fresh allocation for gm_integrate takes no device memory.  A warm-up call
+    on the same kernels comes first: the runtime loads code objects and sets
+    up the per-lane spill area of a kernel on its first launch, which is not
+    the library's allocation."""
+    import torch
+    d = 8
+    cap = 1 << 17
+    need = gm.workspace_bytes(d, cap, 0)
+    assert 16 << 20 < need <= SCRATCH
+    p = W.family_params(W.GAUSSIAN, d, seed=5)
+    gm.integrate_noalloc(W.GAUSSIAN, p, *W.unit_box(d), 1e-5, 1e-16, cap)  # warm-up
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    p = W.family_params(W.GAUSSIAN, d, seed=6)
+    I, E, st = gm.integrate_noalloc(W.GAUSSIAN, p, *W.unit_box(d), 1e-5, 1e-16, cap)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert st in (gm.OK, gm.MAX_REGIONS)
+    assert free0 - free1 < 1 << 20, (free0, free1, need)
