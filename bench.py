@@ -139,19 +139,20 @@ def run_cases(gm, cases):
     return out
 
 
-def cpu_baseline(budget_s: float):
-    """The serial oracle on a bounded sample: the 12 d = 8 cases at rel_tol
-    1e-3 and 1e-5 (full runs), whole passes over them repeated while another
-    pass fits the budget (all passes counted)."""
-    from oracle import oracle as O
-    from paper_2511_01573_amd import workloads as W
-    cases = W.config2(taus=(1e-3, 1e-5))
-    evals = 0
-    secs = 0.0
-    names = [c["name"] for c in cases]
-    passes = 0
-    pass_s = 0.0
-    # whole passes only (every case equally represented); the first one always
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_passes(O, cases, budget_s: float):
+    """Whole passes over the cases (every case equally represented), repeated
+    while another pass fits the budget; the first pass always runs."""
+    evals, secs, passes, pass_s = 0, 0.0, 0, 0.0
     while passes == 0 or secs + pass_s <= budget_s:
         t_pass = 0.0
         for c in cases:
@@ -163,10 +164,35 @@ def cpu_baseline(budget_s: float):
         secs += t_pass
         pass_s = t_pass
         passes += 1
+    return evals, secs, passes
+
+
+def cpu_baseline(budget_s: float):
+    """The CPU oracle on a bounded sample: the 12 d = 8 cases at rel_tol 1e-3
+    and 1e-5 (full runs), whole passes repeated while another pass fits the
+    budget.  The serial build (one core) is the baseline; the OpenMP build
+    (per-region evaluation on every core the process may use, reductions
+    serial, the same bits) runs the same sample in half the budget."""
+    from oracle import oracle as O
+    from paper_2511_01573_amd import workloads as W
+    cases = W.config2(taus=(1e-3, 1e-5))
+    O.use_openmp(False)
+    evals, secs, passes = _oracle_passes(O, cases, budget_s)
+    try:
+        threads = O.use_openmp(True)
+        oev, osecs, opasses = _oracle_passes(O, cases, budget_s / 2)
+    finally:
+        O.use_openmp(False)
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        allowed = os.cpu_count()
     return {"value": evals / secs, "unit": "integrand evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{passes} pass(es) over the {len(names)} full oracle runs of the d=8 "
+            "model": _cpu_model(), "nproc": allowed,
+            "omp": {"value": oev / osecs, "cores": threads, "passes": opasses},
+            "sample": f"{passes} pass(es) over the {len(cases)} full oracle runs of the d=8 "
                       f"workload at rel_tol 1e-3/1e-5 (6 families x 2); {evals} evals in "
-                      f"{secs:.1f} s, serial C, 1 thread"}
+                      f"{secs:.1f} s, serial C -O3, 1 thread"}
 
 
 def bench_batch(gm, W, closed_forms):

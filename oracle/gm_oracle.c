@@ -16,9 +16,15 @@
  * degree-5 rule embedded in the same nodes.  Where the paper is silent the
  * readings are stated at each function.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared -lm
+ * Build: gcc -O3 -std=c11 -ffp-contract=off -fPIC -shared -lm (serial); the
+ * all-cores CPU baseline adds -fopenmp (only the per-region evaluation loop of
+ * an iteration runs in parallel; results are bitwise those of the serial build).
  */
 #include "gm_oracle.h"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include <math.h>
 #include <stdlib.h>
@@ -1030,7 +1036,6 @@ static int phase_eval(gmo_run* r) {
   int64_t i;
   int d = r->d;
   ksum Is = r->Ifin, Es = r->Efin;
-  double out[16 + 32];
   r->iter++;
   r->stats[GMO_ST_ITERS] = r->iter;
   r->stats[GMO_ST_REGIONS] += r->n;
@@ -1039,29 +1044,43 @@ static int phase_eval(gmo_run* r) {
                                                     : gmo_num_nodes(d));
   r->stats[GMO_ST_ACTIVE] = r->n;
   if (r->n > r->stats[GMO_ST_MAX_ACTIVE]) r->stats[GMO_ST_MAX_ACTIVE] = r->n;
-  for (i = 0; i < r->n; ++i) {
-    int rc;
-    if (r->rule == 1)
-      rc = gmo_rule_gk(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
-                       out);
-    else if (r->rule == 2)
-      rc = gmo_rule9(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
-                     r->err_model, out);
-    else
-      rc = gmo_rule(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
-                    out);
-    if (rc == GMO_NONFINITE) {
+  /* Every region is evaluated on its own; the OpenMP build (the CPU
+     baseline's all-cores variant) spreads this loop over threads, and every
+     sum below stays serial in store order, so both builds give the same bits. */
+  {
+    int nonfinite = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : nonfinite)
+#endif
+    for (i = 0; i < r->n; ++i) {
+      int rc;
+      double o[16 + 32];
+      if (r->rule == 1)
+        rc = gmo_rule_gk(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i],
+                         r->vol_omega, o);
+      else if (r->rule == 2)
+        rc = gmo_rule9(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
+                       r->err_model, o);
+      else
+        rc = gmo_rule(r->fam, d, r->params, r->c + i * d, r->h + i * d, r->lvl[i], r->vol_omega,
+                      o);
+      if (rc == GMO_NONFINITE) {
+        nonfinite = 1;
+        continue;
+      }
+      r->Q[i] = o[0];
+      r->err[i] = o[1];
+      r->escl[i] = o[5];
+      r->axis[i] = (int32_t)o[2];
+      r->geo[i] = (unsigned char)o[3];
+    }
+    if (nonfinite) {
       r->I = NAN;
       r->E = NAN;
       r->status = GMO_NONFINITE;
       trace_push(r, r->n, 0);
       return r->status;
     }
-    r->Q[i] = out[0];
-    r->err[i] = out[1];
-    r->escl[i] = out[5];
-    r->axis[i] = (int32_t)out[2];
-    r->geo[i] = (unsigned char)out[3];
   }
   for (i = 0; i < r->n; ++i) ks_add(&Is, r->Q[i]);
   for (i = 0; i < r->n; ++i) ks_add(&Es, r->err[i]);
@@ -1477,4 +1496,13 @@ int gmo_integrate_batch_rule(int n, const int* fam, const double* params, const 
   }
   free(runs);
   return worst;
+}
+
+/* Threads the evaluation loop uses (1 in the serial build). */
+int gmo_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -180,6 +180,9 @@ int gmo_integrate_batch_rule(int n, const int* fam, const double* params, const 
                              int max_iters, int rule, int err_model, double* out_est,
                              double* out_err, int* out_status, int64_t* out_iters);
 
+/* Threads of the per-region evaluation loop: 1 unless built with OpenMP. */
+int gmo_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

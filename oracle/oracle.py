@@ -16,6 +16,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+# the same source built with -fopenmp: the CPU baseline's all-cores variant
+# (per-region evaluation in parallel, every reduction serial: the same bits)
+LIB_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
 SRC = os.path.join(HERE, "gm_oracle.c")
 
 OSCILLATORY, PRODUCT_PEAK, CORNER_PEAK, GAUSSIAN, C0, DISCONTINUOUS, POLY = range(1, 8)
@@ -37,22 +40,41 @@ STAT_NAMES = ["iterations", "regions", "evals", "active", "finished", "max_activ
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-ffp-contract=off: no implicit FMA)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared",
-               "-o", LIB_PATH, SRC, "-lm"]
-        subprocess.check_call(cmd)
+    """Compile the oracle with gcc (-O3, -ffp-contract=off: no implicit FMA),
+    serial and with OpenMP."""
+    hdr = os.path.join(HERE, "gm_oracle.h")
+    newest = max(os.path.getmtime(SRC), os.path.getmtime(hdr))
+    for path, extra in ((LIB_PATH, []), (LIB_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < newest:
+            cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared"] + \
+                extra + ["-o", path, SRC, "-lm"]
+            subprocess.check_call(cmd)
     return LIB_PATH
 
 
 _lib = None
+_libs = {}
+
+
+def use_openmp(on: bool) -> int:
+    """Route every following oracle call through the OpenMP build (on) or the
+    serial build (off); returns the thread count of the selected build."""
+    global _lib
+    _lib = _load(LIB_OMP_PATH if on else LIB_PATH)
+    return int(_lib.gmo_threads())
 
 
 def lib():
     global _lib
     if _lib is None:
+        _lib = _load(LIB_PATH)
+    return _lib
+
+
+def _load(path):
+    if path not in _libs:
         build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
         i32p = C.POINTER(C.c_int32)
@@ -124,8 +146,10 @@ def lib():
         L.gmo_integrate_batch.restype = C.c_int
         L.gmo_integrate_batch.argtypes = [C.c_int, ip, dp, ip, dp, dp, dp, dp, C.c_int64, C.c_int,
                                           C.c_int, dp, dp, ip, i64p]
-        _lib = L
-    return _lib
+        L.gmo_threads.restype = C.c_int
+        L.gmo_threads.argtypes = []
+        _libs[path] = L
+    return _libs[path]
 
 
 def _d(a):

@@ -19,6 +19,7 @@ import pytest
 
 import closed_forms as cf
 from oracle import oracle as O
+from paper_2511_01573_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_integrands_d3.json")
 
@@ -356,3 +357,29 @@ def test_c0_u_partial_closed_form_flips_sign_across_the_peak():
             assert abs(float(g[2])) < 1e-30
         else:
             assert np.sign(float(g[2])) == sgn
+
+
+@pytest.mark.parametrize("fam,d,rule_id", [(1, 5, 0), (2, 4, 0), (3, 6, 0), (4, 5, 0), (5, 4, 0),
+                                           (6, 5, 0), (4, 6, 2), (2, 3, 1)])
+def test_openmp_build_gives_the_serial_bits(fam, d, rule_id):
+    """The CPU baseline's all-cores build (-fopenmp: an iteration's regions
+    are evaluated in parallel, every sum stays serial in store order) returns
+    exactly the serial oracle's run: estimate, error, status, counts and the
+    final active set."""
+    p = W.family_params(fam, d, seed=640 + fam + 10 * d)
+    runs = []
+    try:
+        for omp in (False, True):
+            threads = O.use_openmp(omp)
+            assert (threads > 1) == omp or os.cpu_count() == 1
+            tau = 1e-14 if rule_id == O.GAUSS_KRONROD else 1e-6
+            r = O.Run(fam, p, *unit(d), tau, 1e-16, 1 << 20, init_log2=6, rule_id=rule_id)
+            r.run()
+            res = r.result()
+            act = r.active()
+            runs.append((res["I"], res["E"], res["status"], res["regions"], res["iterations"],
+                         [np.asarray(v).tobytes() for v in act.values()]))
+    finally:
+        O.use_openmp(False)
+    assert runs[0] == runs[1]
+    assert runs[0][3] > 500  # several iterations, hundreds of regions and more
