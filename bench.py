@@ -566,7 +566,7 @@ def headline(full: dict) -> dict:
     h["roofline"] = {k: v for k, v in r.items()
                      if k in ("bound", "kernel", "achieved", "peak", "unit", "frac", "traffic",
                               "algorithmic_bytes_per_launch", "rule_avg_launch_ms",
-                              "rule_evals_per_s", "flops_per_eval")}
+                              "rule_launches", "rule_evals_per_s", "flops_per_eval")}
     if "split_compaction" in full:
         sc = full["split_compaction"]
         h["split_compaction"] = {"bound": "hbm", "achieved": S(sc["achieved_GBps"]),
