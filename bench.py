@@ -268,9 +268,12 @@ def bench_batch(gm, W, closed_forms):
 
 def bench_config3(gm, W, closed_forms, log2cap: int):
     """d = 12 and 16, corner peak and product peak, rel_tol 1e-4, region store
-    of 2^log2cap rows (the high-dimensional, many-lanes-per-region regime)."""
+    of 2^log2cap rows (the high-dimensional, many-lanes-per-region regime),
+    each after a warm-up run of the same integral."""
     out = []
     for c in W.config3(max_regions=1 << log2cap):
+        gm.integrate(c["family"], c["params"], c["lo"], c["hi"], c["rel_tol"], c["abs_tol"],
+                     c["max_regions"])
         d = len(c["lo"])
         gm.set_option("timing", 1)
         t0 = time.perf_counter()
@@ -280,10 +283,15 @@ def bench_config3(gm, W, closed_forms, log2cap: int):
         s = gm.last_stats()
         gm.set_option("timing", 0)
         ex = float(closed_forms.exact(c["family"], c["params"][:d], c["params"][d:]))
+        rule_s = max(s["rule_ms"] * 1e-3, 1e-12)
         out.append({"name": c["name"], "status": st, "seconds": dt, "evals": s["evals"],
                     "regions": s["regions_evaluated"], "iterations": s["iterations"],
                     "max_active": s["max_active"], "evals_per_s": s["evals"] / dt,
-                    "rule_evals_per_s": s["evals"] / max(s["rule_ms"] * 1e-3, 1e-12),
+                    "regions_per_s": s["regions_evaluated"] / dt,
+                    "rule_evals_per_s": s["evals"] / rule_s,
+                    # the corner sweep (2^d of the N(d) nodes) costs what it costs at d = 8
+                    "rule_frac": s["evals"] * FLOPS_PER_EVAL[c["family"]] / rule_s / 1e12
+                                 / FP64_VECTOR_PEAK_TFLOPS,
                     "rel_err_vs_closed_form": abs(I - ex) / abs(ex), "E_over_I": E / abs(I)})
     return out
 
@@ -591,7 +599,9 @@ def headline(full: dict) -> dict:
     if "config3" in full:
         h["config3"] = {c["name"]: {"status": c["status"], "s": S(c["seconds"], 3),
                                     "regions": c["regions"], "max_active": c["max_active"],
-                                    "rule_evals_per_s": S(c["rule_evals_per_s"], 3),
+                                    "evals_per_s": S(c["evals_per_s"], 3),
+                                    "regions_per_s": S(c["regions_per_s"], 3),
+                                    "rule_frac": S(c["rule_frac"], 3),
                                     "rel_err": S(c["rel_err_vs_closed_form"], 2)}
                         for c in full["config3"]}
     if "degree9" in full:

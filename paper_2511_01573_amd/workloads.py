@@ -72,12 +72,23 @@ def config2(taus=(1e-3, 1e-5, 1e-7), reps=1, max_regions=1 << 24):
     return out
 
 
-def config3(dims=(12, 16), tau=1e-4, max_regions=1 << 26):
-    """d = 12 and 16: corner peak and product peak, seeded as config 2."""
+# Sum of a_j of the d = 12 / 16 cases at rel_tol 1e-4, calibrated once on the
+# GPU so that each run converges inside a store of 2^27 regions with about
+# 1e8 regions at its largest (d = 12: corner peak 2.2e8 regions evaluated,
+# 7.9e7 active at the peak; product peak 1.3e8 / 4.3e7; d = 16: corner peak
+# 1.0e8 / 3.5e7, product peak 5.1e7 / 2.0e7, where 25 no longer fits), then
+# frozen.
+DIFFICULTY_C3 = {(CORNER_PEAK, 12): 4.0, (PRODUCT_PEAK, 12): 40.0,
+                 (CORNER_PEAK, 16): 2.0, (PRODUCT_PEAK, 16): 20.0}
+
+
+def config3(dims=(12, 16), tau=1e-4, max_regions=1 << 27):
+    """d = 12 and 16: corner peak and product peak, seeded as config 2 with
+    the sums of a_j of DIFFICULTY_C3 (region store of 2^27 regions)."""
     out = []
     for d in dims:
         for fam in (CORNER_PEAK, PRODUCT_PEAK):
-            p = family_params(fam, d, 1000 * fam + d, DIFFICULTY_D8[fam])
+            p = family_params(fam, d, 1000 * fam + d, DIFFICULTY_C3[(fam, d)])
             out.append(dict(family=fam, params=p, lo=np.zeros(d), hi=np.ones(d), rel_tol=tau,
                             abs_tol=1e-16, max_regions=max_regions, name=f"{NAMES[fam]}_d{d}"))
     return out

@@ -52,7 +52,8 @@ def _full_result():
             "fd_all_ok": True, "fd_max_err_rel_to_max": 2.5e-6}
     c3 = [{"name": n, "status": 0, "seconds": 3.57, "evals": 6608123456789,
            "regions": 100123456, "iterations": 40, "max_active": 35123456,
-           "evals_per_s": 1.87e12, "rule_evals_per_s": 2.1e12, "rel_err_vs_closed_form": 6.1e-6,
+           "evals_per_s": 1.87e12, "regions_per_s": 2.8e7, "rule_evals_per_s": 2.1e12,
+           "rule_frac": 0.4512345, "rel_err_vs_closed_form": 6.1e-6,
            "E_over_I": 9.9e-5}
           for n in ("corner_peak_d12", "product_peak_d12", "corner_peak_d16", "product_peak_d16")]
     d9 = {"totals": {k: {"seconds": 0.0135, "evals": 3712345678, "regions": 3412345,
