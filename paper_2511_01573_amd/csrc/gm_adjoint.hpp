@@ -18,14 +18,16 @@ struct AdjArgs {
 };
 
 using AdjFn = void (*)(AdjArgs);
-// One per family translation unit (r9: the degree-9 rule's nodes and weights);
-// nullptr for the polynomial (no parameters).
-AdjFn adjoint_kernel_f1(int d, bool r9);
-AdjFn adjoint_kernel_f2(int d, bool r9);
-AdjFn adjoint_kernel_f3(int d, bool r9);
-AdjFn adjoint_kernel_f4(int d, bool r9);
-AdjFn adjoint_kernel_f5(int d, bool r9);
-AdjFn adjoint_kernel_f6(int d, bool r9);
-AdjFn adjoint_kernel_f7(int d, bool r9);
+// One per family translation unit (r9: the degree-9 rule's nodes and weights;
+// part: the node group a launch covers, 0 = the degree-7 node set (classes
+// 1-5), 2 = the degree-9 rule's classes 6-8); nullptr for the polynomial (no
+// parameters) and for part 2 of the degree-7 rule.
+AdjFn adjoint_kernel_f1(int d, bool r9, int part);
+AdjFn adjoint_kernel_f2(int d, bool r9, int part);
+AdjFn adjoint_kernel_f3(int d, bool r9, int part);
+AdjFn adjoint_kernel_f4(int d, bool r9, int part);
+AdjFn adjoint_kernel_f5(int d, bool r9, int part);
+AdjFn adjoint_kernel_f6(int d, bool r9, int part);
+AdjFn adjoint_kernel_f7(int d, bool r9, int part);
 
 }  // namespace gm

@@ -19,25 +19,38 @@
 
 namespace gm {
 
-__global__ void adjoint_reduce_kernel(const double* partials, int np, int nparam, double* out) {
-  const int j = threadIdx.x;
-  if (j >= nparam) return;
-  dd v = {0.0, 0.0};
-  for (int b = 0; b < np; ++b) {
-    const double* p = partials + ((int64_t)b * 2 * kMaxDim + j) * 2;
-    v = dd_sum(v, dd{p[0], p[1]});
+// Sum of the np block partials of each of the nparam components (double-
+// double, in a fixed order: thread t adds blocks t, t + 256, ... and the 256
+// per-thread sums are combined by a fixed tree).
+__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const double* partials, int np,
+                                                             int nparam, double* out) {
+  __shared__ dd sh[256];
+  const int t = threadIdx.x;
+  for (int j = 0; j < nparam; ++j) {
+    dd v = {0.0, 0.0};
+    for (int b = t; b < np; b += 256) {
+      const double* p = partials + ((int64_t)b * 2 * kMaxDim + j) * 2;
+      v = dd_sum(v, dd{p[0], p[1]});
+    }
+    sh[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) sh[t] = dd_sum(sh[t], sh[t + s]);
+      __syncthreads();
+    }
+    if (t == 0) out[j] = dd_val(sh[0]);
+    __syncthreads();
   }
-  out[j] = dd_val(v);
 }
 
-static AdjFn adj_fn(int d, int fam, bool r9) {
+static AdjFn adj_fn(int d, int fam, bool r9, int part) {
   switch (fam) {
-    case 1: return adjoint_kernel_f1(d, r9);
-    case 2: return adjoint_kernel_f2(d, r9);
-    case 3: return adjoint_kernel_f3(d, r9);
-    case 4: return adjoint_kernel_f4(d, r9);
-    case 5: return adjoint_kernel_f5(d, r9);
-    case 6: return adjoint_kernel_f6(d, r9);
+    case 1: return adjoint_kernel_f1(d, r9, part);
+    case 2: return adjoint_kernel_f2(d, r9, part);
+    case 3: return adjoint_kernel_f3(d, r9, part);
+    case 4: return adjoint_kernel_f4(d, r9, part);
+    case 5: return adjoint_kernel_f5(d, r9, part);
+    case 6: return adjoint_kernel_f6(d, r9, part);
     default: return nullptr;
   }
 }
@@ -74,32 +87,44 @@ extern "C" int gm_integrate_grad(int integrand_id, const double* params, int d, 
     fill_params(integrand_id, d, params, A.P);
     fill_consts(d, A.K);
     A.vol_omega = rr.vol_omega;
-    // Partials: leaves first, then the last active set, reduced together.
+    // One launch per node group (classes 1-5 and, for the degree-9 rule, its
+    // classes 6-8) over each region set (the leaf store, then the
+    // last active set); every launch writes its own block partials, reduced
+    // together.
+    const bool r9 = options().rule == 2;
+    const int parts[2] = {0, 2};  // classes 1-5; the degree-9 rule's classes 6-8
+    const int nparts = r9 ? 2 : 1;
     const int64_t n1 = rr.leaf_count, n2 = rr.final_n;
     const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((n1 + kAdjBlock - 1) / kAdjBlock, kMaxAdjGrid / 2));
     const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((n2 + kAdjBlock - 1) / kAdjBlock, kMaxAdjGrid / 2));
+    const int nblocks = nparts * (g1 + g2);
     double* part = nullptr;
     double* dout = nullptr;
-    const size_t pbytes = sizeof(double) * 2 * 2 * kMaxDim * (size_t)(g1 + g2);
+    const size_t pbytes = sizeof(double) * 2 * 2 * kMaxDim * (size_t)nblocks;
     if (hipMalloc(&part, pbytes) != hipSuccess || hipMalloc(&dout, sizeof(double) * 2 * kMaxDim) != hipSuccess) {
       (void)hipGetLastError();
       if (part) (void)hipFree(part);
       return GM_ENOMEM;
     }
-    AdjFn fn = adj_fn(d, integrand_id, options().rule == 2);
-    A.partials = part;
-    A.R = RegionSrc{lv.C, lv.H, lv.L, nullptr, lv.cap, 0, 0};
-    A.n = n1;
-    hipLaunchKernelGGL(fn, dim3(g1), dim3(kAdjBlock), 0, s, A);
-    A.partials = part + (size_t)g1 * 2 * kMaxDim * 2;
-    A.R = RegionSrc{(const double*)(rr.base + rr.lay.C[rr.buf]),
-                    (const double*)(rr.base + rr.lay.H[rr.buf]),
-                    (const uint16_t*)(rr.base + rr.lay.L[rr.buf]),
-                    (const uint8_t*)(rr.base + rr.lay.PAX[rr.buf]), rr.cap, rr.final_npar,
-                    rr.final_split};
-    A.n = n2;
-    hipLaunchKernelGGL(fn, dim3(g2), dim3(kAdjBlock), 0, s, A);
-    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(1), dim3(64), 0, s, part, g1 + g2, 2 * d, dout);
+    const RegionSrc leaves{lv.C, lv.H, lv.L, nullptr, lv.cap, 0, 0};
+    const RegionSrc active{(const double*)(rr.base + rr.lay.C[rr.buf]),
+                           (const double*)(rr.base + rr.lay.H[rr.buf]),
+                           (const uint16_t*)(rr.base + rr.lay.L[rr.buf]),
+                           (const uint8_t*)(rr.base + rr.lay.PAX[rr.buf]), rr.cap, rr.final_npar,
+                           rr.final_split};
+    int64_t blk = 0;
+    for (int pt = 0; pt < nparts; ++pt) {
+      AdjFn fn = adj_fn(d, integrand_id, r9, parts[pt]);
+      for (int set = 0; set < 2; ++set) {
+        const int g = set ? g2 : g1;
+        A.partials = part + (size_t)blk * 2 * kMaxDim * 2;
+        A.R = set ? active : leaves;
+        A.n = set ? n2 : n1;
+        hipLaunchKernelGGL(fn, dim3(g), dim3(kAdjBlock), 0, s, A);
+        blk += g;
+      }
+    }
+    hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(1), dim3(256), 0, s, part, nblocks, 2 * d, dout);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(grad.data(), dout, sizeof(double) * 2 * d, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

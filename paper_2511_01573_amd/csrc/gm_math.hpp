@@ -49,6 +49,12 @@ constexpr double kCosPoly[10] = {-0x1.5ca3b5d23666ap-53, 0x1.ae432cc0bd5d4p-45,
                                  -0x1.27e4fb74f50a4p-22, 0x1.a01a01a0132f7p-16,
                                  -0x1.6c16c16c16b71p-10, 0x1.5555555555554p-5,
                                  -0x1.0000000000000p-1,  0x1.0000000000000p+0};
+// sin r = r (1 + z Q(z)), z = r^2 <= (pi/2)^2
+constexpr double kSinPoly[9] = {-0x1.275f3132d0bb5p-57, 0x1.9507ff1d2eab1p-49,
+                                -0x1.ae7ee3a7e62e7p-41, 0x1.612460b6ab17ep-33,
+                                -0x1.ae64567e733b7p-26, 0x1.71de3a556b9b6p-19,
+                                -0x1.a01a01a01a00dp-13, 0x1.1111111111111p-7,
+                                -0x1.5555555555555p-3};
 constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;
 constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;
 constexpr double kInvLn2 = 0x1.71547652b82fep+0;
@@ -147,6 +153,52 @@ GM_HD void cos_n(const double (&x)[N], double (&y)[N]) {
   }
 }
 
+// sin x with the reduction of cos_n: x = r + k pi, r = rh + rl, sin x =
+// (-1)^k sin r, sin r = rh + (rh z Q(z) + rl (1 - z/2)) with z = rh^2 (the
+// first-order term of rl; its square is below 2^-100 |x|^2).
+template <int N>
+GM_HD void sin_n(const double (&x)[N], double (&y)[N]) {
+  double t[N], kd[N], r1[N], rh[N], rl[N], z[N], q[N], s[N];
+  int32_t k[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    t[i] = fma(x[i], kInvPi, kShift);
+    kd[i] = t[i] - kShift;
+    k[i] = low_word(t[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) r1[i] = fma(-kd[i], kPi_1, x[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) rh[i] = fma(-kd[i], kPi_2, r1[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) rl[i] = fma(-kd[i], kPi_3, fma(-kd[i], kPi_2, r1[i] - rh[i]));
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    z[i] = rh[i] * rh[i];
+    q[i] = kSinPoly[0];
+  }
+#pragma unroll
+  for (int cc = 1; cc < 9; ++cc) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) q[i] = fma(q[i], z[i], kSinPoly[cc]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    s[i] = rh[i] + fma(rh[i] * z[i], q[i], rl[i] * fma(z[i], -0.5, 1.0));
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    y[i] = __hiloint2double(__double2hiint(s[i]) ^ (int)((uint32_t)k[i] << 31),
+                            __double2loint(s[i]));
+#else
+    uint32_t w[2];
+    std::memcpy(w, &s[i], sizeof w);
+    w[1] ^= (uint32_t)k[i] << 31;
+    std::memcpy(&y[i], w, sizeof w);
+#endif
+  }
+}
+
 // 1/x: the hardware reciprocal estimate refined by two Newton steps
 // e = 1 - x r, r += r e (each step squares the relative error), within 1 ulp
 // for |x| in [2^-1022, 2^1022].  Outside that range (reciprocals beyond the
@@ -184,6 +236,13 @@ GM_HD double cos(double x) {
   const double a[1] = {x};
   double y[1];
   cos_n<1>(a, y);
+  return y[0];
+}
+
+GM_HD double sin(double x) {
+  const double a[1] = {x};
+  double y[1];
+  sin_n<1>(a, y);
   return y[0];
 }
 

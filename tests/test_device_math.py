@@ -1,6 +1,7 @@
 """Accuracy of the FP64 exp and cos that the rule kernel uses for its outer
-functions (paper_2511_01573_amd/csrc/gm_math.hpp), compiled for the host from
-the same source, against 50-digit references."""
+functions, and of the sin of the adjoint kernel (paper_2511_01573_amd/csrc/
+gm_math.hpp), compiled for the host from the same source, against 50-digit
+references."""
 from __future__ import annotations
 
 import ctypes as C
@@ -23,7 +24,7 @@ def harness():
                            "-I", os.path.join(ROOT, "paper_2511_01573_amd", "csrc"),
                            os.path.join(ROOT, "tests", "math_harness.cpp"), "-o", so])
     L = C.CDLL(so)
-    for f in (L.gm_test_exp, L.gm_test_cos):
+    for f in (L.gm_test_exp, L.gm_test_cos, L.gm_test_sin):
         f.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_long]
     return L
 
@@ -78,3 +79,27 @@ def test_cos_error_bound(harness):
     big = np.abs(ref) >= 0.5
     rel = err[big] / np.abs(ref[big])
     assert rel.max() <= 2.0 ** -52
+
+
+def test_sin_error_bound(harness):
+    """sin (the oscillatory family's derivative in the adjoint kernel): within
+    1.5 ulp of 1 absolutely and 1.5 ulp relative where |sin x| >= 1/2 (the
+    leading term rh and its correction are rounded once more than cos's), and
+    within 1 ulp near the zeros below pi/2 (no cancellation in the reduction
+    there)."""
+    mp.mp.dps = 60
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.uniform(-10, 10, 3000), rng.uniform(-200, 200, 1000),
+                        rng.uniform(-1e5, 1e5, 300), np.arange(-20, 21) * (np.pi / 2),
+                        [0.0, 1e-300, 2e6, -3e7]])
+    y = call(harness.gm_test_sin, x)
+    ref = np.array([float(mp.sin(mp.mpf(v))) for v in x])
+    err = np.abs(y - ref)
+    assert err.max() <= 1.5 * 2.0 ** -52, (err.max(), x[np.argmax(err)])
+    big = np.abs(ref) >= 0.5
+    rel = err[big] / np.abs(ref[big])
+    assert rel.max() <= 1.5 * 2.0 ** -52
+    small = rng.uniform(-1.5, 1.5, 2000) * 10.0 ** rng.uniform(-12, 0, 2000)
+    ys = call(harness.gm_test_sin, small)
+    refs = [mp.sin(mp.mpf(v)) for v in small]
+    assert ulp_err(ys, refs).max() <= 1.0
