@@ -661,15 +661,15 @@ RuleKernelFn gk_kernel(int d, int fam, bool batch) {
   }
 }
 
-RuleKernelFn r9_kernel(int d, int fam, bool batch) {
+RuleKernelFn r9_kernel(int d, int fam, bool batch, bool wide) {
   switch (fam) {
-    case 1: return rule9_kernel_f1(d, batch);
-    case 2: return rule9_kernel_f2(d, batch);
-    case 3: return rule9_kernel_f3(d, batch);
-    case 4: return rule9_kernel_f4(d, batch);
-    case 5: return rule9_kernel_f5(d, batch);
-    case 6: return rule9_kernel_f6(d, batch);
-    case 7: return rule9_kernel_f7(d, batch);
+    case 1: return rule9_kernel_f1(d, batch, wide);
+    case 2: return rule9_kernel_f2(d, batch, wide);
+    case 3: return rule9_kernel_f3(d, batch, wide);
+    case 4: return rule9_kernel_f4(d, batch, wide);
+    case 5: return rule9_kernel_f5(d, batch, wide);
+    case 6: return rule9_kernel_f6(d, batch, wide);
+    case 7: return rule9_kernel_f7(d, batch, wide);
     default: return nullptr;
   }
 }
@@ -698,7 +698,7 @@ int64_t nodes_per_region(int d) {
 
 hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, hipStream_t s) {
   RuleKernelFn fn = log2l == kMapGk    ? gk_kernel(d, fam, false)
-                    : log2l >= kMapR9 ? r9_kernel(d, fam, false)
+                    : log2l >= kMapR9 ? r9_kernel(d, fam, false, log2l - kMapR9 != rule9_log2l(d))
                                       : rule_kernel(d, fam, log2l, false);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kRuleBlockSize), 0, s, a);
@@ -718,7 +718,11 @@ constexpr int64_t kTargetLanes = 131072;
 
 int choose_mapping(int d, int64_t n) {
   if (g_opt.rule == 1) return kMapGk;
-  if (g_opt.rule == 2) return kMapR9 + rule9_log2l(d);
+  if (g_opt.rule == 2) {
+    // the wide mapping while the default one would leave the GPU mostly idle
+    const bool wide = (n << rule9_log2l(d)) < kTargetLanes;
+    return kMapR9 + (wide ? rule9_log2l_wide(d) : rule9_log2l(d));
+  }
   const int forced = g_opt.lanes_per_region;
   if (forced > 0) {
     int l = -1;

@@ -253,14 +253,19 @@ constexpr int kGkMaxDim = 6;
 
 // Degree-9 fully symmetric rule kernels, one launcher per family, 2 <= d <= 16
 // (batch-store kernels: d <= kBatchMaxDim); 2^rule9_log2l(d) lanes of one
-// wavefront per region (at least one corner and at most 64 lanes per region).
-RuleKernelFn rule9_kernel_f1(int d, bool batch);
-RuleKernelFn rule9_kernel_f2(int d, bool batch);
-RuleKernelFn rule9_kernel_f3(int d, bool batch);
-RuleKernelFn rule9_kernel_f4(int d, bool batch);
-RuleKernelFn rule9_kernel_f5(int d, bool batch);
-RuleKernelFn rule9_kernel_f6(int d, bool batch);
-RuleKernelFn rule9_kernel_f7(int d, bool batch);
+// wavefront per region (at least one corner and at most 64 lanes per region),
+// or 2^rule9_log2l_wide(d) with `wide` (single-store kernels only).
+RuleKernelFn rule9_kernel_f1(int d, bool batch, bool wide);
+RuleKernelFn rule9_kernel_f2(int d, bool batch, bool wide);
+RuleKernelFn rule9_kernel_f3(int d, bool batch, bool wide);
+RuleKernelFn rule9_kernel_f4(int d, bool batch, bool wide);
+RuleKernelFn rule9_kernel_f5(int d, bool batch, bool wide);
+RuleKernelFn rule9_kernel_f6(int d, bool batch, bool wide);
+RuleKernelFn rule9_kernel_f7(int d, bool batch, bool wide);
 constexpr int rule9_log2l(int d) { return d - 5 < 2 ? 2 : (d - 5 > 6 ? 6 : d - 5); }
+// The wide mapping of the degree-9 kernel for active sets too small to fill
+// the GPU at rule9_log2l(d): up to 64 lanes per region (at least one corner
+// per lane).
+constexpr int rule9_log2l_wide(int d) { return d < 6 ? d : 6; }
 
 }  // namespace gm

@@ -62,8 +62,9 @@ hipError_t launch_rule(int d, int fam, int log2l, const RuleArgs& a, int grid, h
 // else log2 of the lanes per region.
 int choose_mapping(int d, int64_t n);
 RuleKernelFn rule_kernel(int d, int fam, int log2l, bool batch);
-// Degree-9 rule kernel of (d, family): single-store or batch-store variant.
-RuleKernelFn r9_kernel(int d, int fam, bool batch);
+// Degree-9 rule kernel of (d, family): single-store or batch-store variant;
+// `wide`: the single-store kernel with 2^rule9_log2l_wide(d) lanes per region.
+RuleKernelFn r9_kernel(int d, int fam, bool batch, bool wide = false);
 // Gauss-Kronrod rule kernel of (d, family), d <= kGkMaxDim.
 RuleKernelFn gk_kernel(int d, int fam, bool batch);
 // Nodes of the rule the options select.

@@ -314,32 +314,33 @@ void rule9_kernel(RuleArgs A) {
 #define GM_R9_CAT(a, b) GM_R9_CAT2(a, b)
 
 template <int D>
-static RuleKernelFn r9_pick(bool batch) {
+static RuleKernelFn r9_pick(bool batch, bool wide) {
   if constexpr (D <= kBatchMaxDim) {
     if (batch) return rule9_kernel<D, GM_RULE_FAMILY, rule9_log2l(D), true>;
   } else {
     if (batch) return nullptr;
   }
+  if (wide) return rule9_kernel<D, GM_RULE_FAMILY, rule9_log2l_wide(D), false>;
   return rule9_kernel<D, GM_RULE_FAMILY, rule9_log2l(D), false>;
 }
 
-RuleKernelFn GM_R9_CAT(rule9_kernel_f, GM_RULE_FAMILY)(int d, bool batch) {
+RuleKernelFn GM_R9_CAT(rule9_kernel_f, GM_RULE_FAMILY)(int d, bool batch, bool wide) {
   switch (d) {
-    case 2: return r9_pick<2>(batch);
-    case 3: return r9_pick<3>(batch);
-    case 4: return r9_pick<4>(batch);
-    case 5: return r9_pick<5>(batch);
-    case 6: return r9_pick<6>(batch);
-    case 7: return r9_pick<7>(batch);
-    case 8: return r9_pick<8>(batch);
-    case 9: return r9_pick<9>(batch);
-    case 10: return r9_pick<10>(batch);
-    case 11: return r9_pick<11>(batch);
-    case 12: return r9_pick<12>(batch);
-    case 13: return r9_pick<13>(batch);
-    case 14: return r9_pick<14>(batch);
-    case 15: return r9_pick<15>(batch);
-    case 16: return r9_pick<16>(batch);
+    case 2: return r9_pick<2>(batch, wide);
+    case 3: return r9_pick<3>(batch, wide);
+    case 4: return r9_pick<4>(batch, wide);
+    case 5: return r9_pick<5>(batch, wide);
+    case 6: return r9_pick<6>(batch, wide);
+    case 7: return r9_pick<7>(batch, wide);
+    case 8: return r9_pick<8>(batch, wide);
+    case 9: return r9_pick<9>(batch, wide);
+    case 10: return r9_pick<10>(batch, wide);
+    case 11: return r9_pick<11>(batch, wide);
+    case 12: return r9_pick<12>(batch, wide);
+    case 13: return r9_pick<13>(batch, wide);
+    case 14: return r9_pick<14>(batch, wide);
+    case 15: return r9_pick<15>(batch, wide);
+    case 16: return r9_pick<16>(batch, wide);
     default: return nullptr;
   }
 }
