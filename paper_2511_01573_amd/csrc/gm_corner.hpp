@@ -115,4 +115,20 @@ __device__ __forceinline__ double chain_tail(double s, const double* tc, int k0)
   return s;
 }
 
+// s[q] (+) tc[k] for k = k0 .. k1 - 1 in order, for N chains at once, with the
+// terms in registers: every index stays compile-time and the runtime bounds
+// select which steps apply.
+template <int D, int FAM, int N>
+__device__ __forceinline__ void chain_from(double (&s)[N], const double (&tc)[D], int k0, int k1) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const bool on = k >= k0 && k < k1;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const double t = Fam<FAM>::comb(s[q], tc[k]);
+      s[q] = on ? t : s[q];
+    }
+  }
+}
+
 }  // namespace gm

@@ -272,20 +272,21 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
     __syncthreads();
     const double f0 = F::template outer<D>(P, full);
     KSum S2 = {0.0, 0.0}, S3 = {0.0, 0.0}, S4 = {0.0, 0.0}, S5 = {0.0, 0.0};
-    // Classes 2-4 as work items.
+    // Classes 2-4 as work items.  The chains run over the lane's own centre
+    // terms (registers) with the runtime bounds as predicates, so an item's
+    // nodes advance together instead of waiting on one LDS load per step.
     for (int it = s; it < NITEM; it += L) {
       if (it < D) {
         const int i = it;
         const double ci = sl.c[i], hi = sl.h[i];
         const double v[4] = {F::term(P, i, fma(K.lam2, hi, ci)), F::term(P, i, fma(-K.lam2, hi, ci)),
                              F::term(P, i, fma(K.lam3, hi, ci)), F::term(P, i, fma(-K.lam3, hi, ci))};
-        double f[4];
+        double a[4], f[4];
         const double pci = sl.pc[i];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double s0 = (i == 0) ? v[q] : F::comb(pci, v[q]);
-          f[q] = F::template outer<D>(P, chain_tail<D, FAM>(s0, sl.tc, i + 1));
-        }
+        for (int q = 0; q < 4; ++q) a[q] = (i == 0) ? v[q] : F::comb(pci, v[q]);
+        chain_from<D, FAM, 4>(a, tc, i + 1, D);
+        F::template outer_n<D, 4>(P, a, f);
         ks_add(S2, f[0]);
         ks_add(S2, f[1]);
         ks_add(S3, f[2]);
@@ -300,15 +301,20 @@ __global__ __launch_bounds__(kRuleBlock) void rule_wpr_kernel(RuleArgs A) {
         const double ci = sl.c[i], hi = sl.h[i], cj = sl.c[j], hj = sl.h[j];
         const double tj[2] = {F::term(P, j, fma(K.lam4, hj, cj)), F::term(P, j, fma(-K.lam4, hj, cj))};
         const double pci = sl.pc[i];
+        double m[2];
 #pragma unroll
         for (int si = 0; si < 2; ++si) {
           const double ti = F::term(P, i, fma(si ? -K.lam4 : K.lam4, hi, ci));
-          double m = (i == 0) ? ti : F::comb(pci, ti);
-          for (int k = i + 1; k < j; ++k) m = F::comb(m, sl.tc[k]);
-#pragma unroll
-          for (int sj = 0; sj < 2; ++sj)
-            ks_add(S4, F::template outer<D>(P, chain_tail<D, FAM>(F::comb(m, tj[sj]), sl.tc, j + 1)));
+          m[si] = (i == 0) ? ti : F::comb(pci, ti);
         }
+        chain_from<D, FAM, 2>(m, tc, i + 1, j);
+        double a[4] = {F::comb(m[0], tj[0]), F::comb(m[0], tj[1]), F::comb(m[1], tj[0]),
+                       F::comb(m[1], tj[1])};
+        chain_from<D, FAM, 4>(a, tc, j + 1, D);
+        double f[4];
+        F::template outer_n<D, 4>(P, a, f);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ks_add(S4, f[q]);
       }
     }
     // Class 5: this lane's 2^(D - LOG2L) corners.
