@@ -40,6 +40,8 @@ constexpr int kTileThreads = 256;  // 4 regions per thread per tile
 constexpr int kMaxRuleGrid = 16384;
 constexpr int kPruneBins = 66;  // budget factors 2^1 .. 2^64, bin 65 = beyond
 constexpr int kMaxTileGrid = 8192;
+// Largest active set whose bookkeeping runs as one workgroup (small_step_kernel).
+constexpr int64_t kSmallStepRegions = 4 * 1024;
 
 struct InitArgs {
   double* C;
@@ -67,26 +69,11 @@ __global__ void init_kernel(InitArgs A) {
   }
 }
 
-// Global reduction of the rule kernel's block partials and the stopping rule.
-__global__ __launch_bounds__(1024) void reduce_kernel(Status* st, const double* partials, int np,
-                                                      int64_t* hist) {
-  if (st->done) return;
-  for (int b = threadIdx.x; b < kPruneBins; b += 1024) hist[b] = 0;
-  dd q = {0.0, 0.0}, e = {0.0, 0.0};
-  for (int p = threadIdx.x; p < np; p += 1024) {
-    q = dd_sum(q, dd{partials[4 * p + 0], partials[4 * p + 1]});
-    e = dd_sum(e, dd{partials[4 * p + 2], partials[4 * p + 3]});
-  }
-  q = wave_sum_dd(q);
-  e = wave_sum_dd(e);
-  __shared__ dd sq[16], se[16];
-  if ((threadIdx.x & 63) == 0) {
-    sq[threadIdx.x >> 6] = q;
-    se[threadIdx.x >> 6] = e;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int w = 1; w < 16; ++w) {
+// Thread 0 of the reduction: the waves' sums, the retired totals, the
+// iteration counters and the stopping rule (Sec. 4).
+__device__ __forceinline__ void reduce_commit(Status* st, dd q, dd e, const dd* sq, const dd* se,
+                                              int nw) {
+  for (int w = 1; w < nw; ++w) {
     q = dd_sum(q, sq[w]);
     e = dd_sum(e, se[w]);
   }
@@ -115,6 +102,42 @@ __global__ __launch_bounds__(1024) void reduce_kernel(Status* st, const double* 
     st->status = GM_MAX_ITERS;
     st->done = 1;
   }
+}
+
+// Global reduction of the rule kernel's block partials and the stopping rule
+// (the body of reduce_kernel and of the fused small-iteration kernel).  The
+// summation order is that of kReduceLanes virtual threads whatever the block
+// size (a divisor of kReduceLanes, a multiple of 64): virtual thread v adds
+// partials v, v + kReduceLanes, ..., the wavefronts' sums are combined in
+// order, so both kernels give the same bits.
+constexpr int kReduceLanes = 1024;
+
+__device__ __forceinline__ void reduce_body(Status* st, const double* partials, int np,
+                                            int64_t* hist) {
+  const int nthr = blockDim.x, tid = threadIdx.x;
+  for (int b = tid; b < kPruneBins; b += nthr) hist[b] = 0;
+  __shared__ dd sq[kReduceLanes / 64], se[kReduceLanes / 64];
+  for (int v = tid; v < kReduceLanes; v += nthr) {
+    dd q = {0.0, 0.0}, e = {0.0, 0.0};
+    for (int p = v; p < np; p += kReduceLanes) {
+      q = dd_sum(q, dd{partials[4 * p + 0], partials[4 * p + 1]});
+      e = dd_sum(e, dd{partials[4 * p + 2], partials[4 * p + 3]});
+    }
+    q = wave_sum_dd(q);
+    e = wave_sum_dd(e);
+    if ((v & 63) == 0) {
+      sq[v >> 6] = q;
+      se[v >> 6] = e;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) reduce_commit(st, sq[0], se[0], sq, se, kReduceLanes / 64);
+}
+
+__global__ __launch_bounds__(1024) void reduce_kernel(Status* st, const double* partials, int np,
+                                                      int64_t* hist) {
+  if (st->done) return;
+  reduce_body(st, partials, np, hist);
 }
 
 struct ClassifyArgs {
@@ -148,11 +171,13 @@ __device__ __forceinline__ int prune_level(double err, double T, int lvl) {
 // overflows the store the scan kernel picks the smallest sufficient factor
 // 2^k and the second pass (SECOND) classifies again with err <= T 2^(k - lvl)
 // added to the retire test.
+// The tiles tile0, tile0 + tstride, ... of the active set (the body of
+// classify_kernel, and of the fused small-iteration kernel with one block);
+// blocks of kTileThreads threads.
 template <bool SECOND>
-__global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) {
+__device__ __forceinline__ void classify_tiles(const ClassifyArgs& A, int64_t tile0,
+                                               int64_t tstride) {
   const Status* st = A.st;
-  if (st->done) return;
-  if (SECOND && !st->reclassify) return;
   const int64_t n = st->n_active;
   const double T = st->T;
   const double aI = fabs(st->I);
@@ -169,7 +194,7 @@ __global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) 
     for (int b = threadIdx.x; b < kPruneBins; b += kTileThreads) shist[b] = 0;
     __syncthreads();
   }
-  for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (int64_t tile = tile0; tile < nt; tile += tstride) {
     int64_t keep = 0;
     dd q = {0.0, 0.0}, e = {0.0, 0.0};
 #pragma unroll
@@ -222,20 +247,32 @@ __global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) 
   }
 }
 
+template <bool SECOND>
+__global__ __launch_bounds__(kTileThreads) void classify_kernel(ClassifyArgs A) {
+  if (A.st->done) return;
+  if (SECOND && !A.st->reclassify) return;
+  classify_tiles<SECOND>(A, blockIdx.x, gridDim.x);
+}
+
 // Exclusive scan of the per-tile keep counts (one workgroup), capacity and
 // precision checks, and the commit of the retired partial sums.  When the
 // kept set overflows the store and pruning is on, the first pass picks the
 // budget factor and leaves the commit to the second pass (SECOND), which runs
 // after the second classification.
 template <bool SECOND>
-__global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* TK, int64_t* TOFF,
-                                                    const double* TQ, const double* TE,
-                                                    const int64_t* HIST) {
-  if (st->done) return;
-  if (SECOND && !st->reclassify) return;
+__device__ void scan_commit(Status* st, int64_t total, dd tq, dd te, const int64_t* HIST);
+
+// Exclusive scan of the tile counts by one block (the body of scan_kernel and
+// of the fused small-iteration kernel; any block size up to 1024 threads, a
+// multiple of 64): thread t takes `per` consecutive tiles.
+template <bool SECOND>
+__device__ __forceinline__ void scan_body(Status* st, const int64_t* TK, int64_t* TOFF,
+                                          const double* TQ, const double* TE,
+                                          const int64_t* HIST) {
+  const int nthr = blockDim.x;
   const int64_t n = st->n_active;
   const int64_t nt = (n + kTile - 1) / kTile;
-  const int64_t per = (nt + 1023) / 1024;
+  const int64_t per = (nt + nthr - 1) / nthr;
   const int64_t t0 = (int64_t)threadIdx.x * per;
   const int64_t t1 = t0 + per < nt ? t0 + per : nt;
   int64_t sum = 0;
@@ -264,7 +301,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* T
   }
   __syncthreads();
   int64_t woff = 0, total = 0;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < nthr / 64; ++i) {
     if (i < w) woff += wtot[i];
     total += wtot[i];
   }
@@ -275,10 +312,27 @@ __global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* T
   }
   if (threadIdx.x != 0) return;
   dd tq = sq[0], te = se[0];
-  for (int i = 1; i < 16; ++i) {
+  for (int i = 1; i < nthr / 64; ++i) {
     tq = dd_sum(tq, sq[i]);
     te = dd_sum(te, se[i]);
   }
+  scan_commit<SECOND>(st, total, tq, te, HIST);
+}
+
+template <bool SECOND>
+__global__ __launch_bounds__(1024) void scan_kernel(Status* st, const int64_t* TK, int64_t* TOFF,
+                                                    const double* TQ, const double* TE,
+                                                    const int64_t* HIST) {
+  if (st->done) return;
+  if (SECOND && !st->reclassify) return;
+  scan_body<SECOND>(st, TK, TOFF, TQ, TE, HIST);
+}
+
+// Thread 0 of the scan: capacity and precision checks, the choice of the
+// pruning factor, the commit of the retired sums and the new active count.
+template <bool SECOND>
+__device__ void scan_commit(Status* st, int64_t total, dd tq, dd te, const int64_t* HIST) {
+  const int64_t n = st->n_active;
   if (SECOND) st->reclassify = 0;
   if (total == 0) {
     // a run that pruned and then ran out of regions was limited by the store
@@ -347,11 +401,13 @@ struct ScatterArgs {
 // read from in the next iteration (centre, half-widths, level and the split
 // axis the rule kernel chose); retired regions go to the leaf store in
 // gradient mode.  The dimension is a template parameter so every coordinate
-// load of a region is issued before its stores.
+// load of a region is issued before its stores.  scatter_tiles takes the
+// visits tile0, tile0 + tstride, ... of its tile order (the body of
+// scatter_kernel and of the fused small-iteration kernel).
 template <int D>
-__global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
+__device__ __forceinline__ void scatter_tiles(const ScatterArgs& A, int64_t tile0,
+                                              int64_t tstride) {
   const Status* st = A.st;
-  if (st->done) return;
   const int64_t n = st->n_prev;
   const int out = st->buf, in = 1 - out;
   const int64_t leaf_base = st->leaf_base;
@@ -362,9 +418,25 @@ __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
   uint8_t* __restrict__ Po = A.PAX[out];
   const int64_t cap = A.cap;
   const int64_t nt = (n + kTile - 1) / kTile;
+  // Visiting order: the children of parent q sit at q and q + n_par, in the
+  // first-half tile i and about the second-half tile m + i (m = the first
+  // half's tile count).  Visit v of the grid-stride loop takes the pair's two
+  // tiles at v = 16 (i / 8) + i % 8 and that + 8: blocks eight apart run on one
+  // XCD (workgroups go round-robin over the eight), so the parent records that
+  // the first tile reads are still in that XCD's L2 for the second.  Visits
+  // past either half's end do nothing.
+  const bool paired = R.split != 0;
+  const int64_t m = paired ? (R.npar + kTile - 1) / kTile : nt;
+  const int64_t nv = paired ? 16 * ((m + 7) / 8) : nt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __shared__ int64_t wc[kTile / kTileThreads][kTileThreads / 64];
-  for (int64_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+  for (int64_t v = tile0; v < nv; v += tstride) {
+    int64_t tile = v;
+    if (paired) {
+      const int64_t u = v >> 3, i = (u >> 1) * 8 + (v & 7);
+      tile = (u & 1) ? m + i : i;
+      if ((u & 1) ? tile >= nt : i >= m) continue;  // uniform over the block
+    }
     // Counts of every (row, wavefront) first, one barrier per tile.
     bool keepv[kTile / kTileThreads];
     uint64_t masks[kTile / kTileThreads];
@@ -422,7 +494,37 @@ __global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
   }
 }
 
+template <int D>
+__global__ __launch_bounds__(kTileThreads) void scatter_kernel(ScatterArgs A) {
+  if (A.st->done) return;
+  scatter_tiles<D>(A, blockIdx.x, gridDim.x);
+}
+
+// One iteration's bookkeeping for a small active set in a single workgroup:
+// the reduction and stopping rule, the classification, the scan and the
+// split + compaction of reduce_kernel, classify_kernel<false>, scan_kernel<false>
+// and scatter_kernel, in that order and with the same results, separated by
+// workgroup barriers instead of kernel boundaries (for active sets of a few
+// tiles the four launches cost more than their work).  Not for memory-
+// pressure pruning (its second classification pass).
+template <int D>
+__global__ __launch_bounds__(kTileThreads) void small_step_kernel(Status* st,
+                                                                  const double* partials, int np,
+                                                                  ClassifyArgs ca, ScatterArgs sa) {
+  if (st->done) return;
+  reduce_body(st, partials, np, ca.HIST);
+  __syncthreads();
+  if (st->done) return;
+  classify_tiles<false>(ca, 0, 1);
+  __syncthreads();
+  scan_body<false>(st, ca.TK, sa.TOFF, ca.TQ, ca.TE, ca.HIST);
+  __syncthreads();
+  if (st->done) return;
+  scatter_tiles<D>(sa, 0, 1);
+}
+
 using ScatterFn = void (*)(ScatterArgs);
+using SmallStepFn = void (*)(Status*, const double*, int, ClassifyArgs, ScatterArgs);
 
 static ScatterFn scatter_fn(int d) {
   switch (d) {
@@ -441,6 +543,27 @@ static ScatterFn scatter_fn(int d) {
     case 14: return scatter_kernel<14>;
     case 15: return scatter_kernel<15>;
     case 16: return scatter_kernel<16>;
+    default: return nullptr;
+  }
+}
+
+static SmallStepFn small_step_fn(int d) {
+  switch (d) {
+    case 2: return small_step_kernel<2>;
+    case 3: return small_step_kernel<3>;
+    case 4: return small_step_kernel<4>;
+    case 5: return small_step_kernel<5>;
+    case 6: return small_step_kernel<6>;
+    case 7: return small_step_kernel<7>;
+    case 8: return small_step_kernel<8>;
+    case 9: return small_step_kernel<9>;
+    case 10: return small_step_kernel<10>;
+    case 11: return small_step_kernel<11>;
+    case 12: return small_step_kernel<12>;
+    case 13: return small_step_kernel<13>;
+    case 14: return small_step_kernel<14>;
+    case 15: return small_step_kernel<15>;
+    case 16: return small_step_kernel<16>;
     default: return nullptr;
   }
 }
@@ -758,6 +881,14 @@ static int tile_grid_for(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxTileGrid));
 }
 
+// Grid of the split + compaction: its paired visiting order (scatter_tiles)
+// has up to 16 * ceil(ceil(n / 2 / kTile) / 8) visits for n regions.
+static int scatter_grid_for(int64_t n) {
+  const int64_t m = (n / 2 + kTile - 1) / kTile + 1;
+  const int64_t g = std::max<int64_t>((n + kTile - 1) / kTile, 16 * ((m + 7) / 8));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxTileGrid));
+}
+
 // Leaf store of the gradient mode (SoA, grows on demand).
 struct LeafStore {
   double* C = nullptr;
@@ -1010,6 +1141,13 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
       if (timing) GM_HIP(hipEventRecord(ev[k][0], s));
       GM_HIP(launch_rule(d, fam, map, ra, rg, s));
       if (timing) GM_HIP(hipEventRecord(ev[k][1], s));
+      if (!g_opt.prune && !phases && nb <= kSmallStepRegions) {
+        hipLaunchKernelGGL(small_step_fn(d), dim3(1), dim3(kTileThreads), 0, s, st, ra.partials,
+                           rg, ca, sa);
+        GM_HIP(hipGetLastError());
+        nb = std::min<int64_t>(cap, 2 * nb);
+        continue;
+      }
       hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, st, ra.partials, rg, ca.HIST);
       GM_HIP(hipGetLastError());
       if (phases) GM_HIP(hipEventRecord(ev[k][2], s));
@@ -1026,7 +1164,7 @@ int run_adaptive(int fam, const double* params, int d, const double* lo, const d
                            ca.TE, ca.HIST);
         GM_HIP(hipGetLastError());
       }
-      hipLaunchKernelGGL(scatter_fn(d), dim3(tg), dim3(kTileThreads), 0, s, sa);
+      hipLaunchKernelGGL(scatter_fn(d), dim3(scatter_grid_for(nb)), dim3(kTileThreads), 0, s, sa);
       GM_HIP(hipGetLastError());
       if (phases) GM_HIP(hipEventRecord(ev[k][4], s));
       nb = std::min<int64_t>(cap, 2 * nb);

@@ -117,3 +117,60 @@ def test_determinism():
     a = gm.integrate(4, p, *W.unit_box(6), 1e-7)
     b = gm.integrate(4, p, *W.unit_box(6), 1e-7)
     assert a == b
+
+
+def _run_with_timing(timing, fam, p, lo, hi, tau, max_regions, init_log2, max_iters=10000,
+                     abs_tol=1e-16, grad=False):
+    d = len(lo)
+    gm.set_option("timing", timing)
+    gm.set_option("init_log2_regions", init_log2)
+    gm.set_option("max_iters", max_iters)
+    try:
+        if grad:
+            out = gm.integrate_grad(fam, p, lo, hi, tau, abs_tol, max_regions)
+            return out, None, gm.last_stats()
+        out = gm.integrate(fam, p, lo, hi, tau, abs_tol, max_regions)
+        return out, gm.last_active(d), gm.last_stats()
+    finally:
+        gm.set_option("timing", 0)
+        gm.set_option("init_log2_regions", 12)
+        gm.set_option("max_iters", 10000)
+
+
+@pytest.mark.parametrize("case", ["d3_deep", "d8_gauss", "d5_cap", "d3_max_iters",
+                                  "nonfinite", "precision", "grad_d4"])
+def test_small_iteration_kernel_gives_the_four_kernel_bits(case):
+    """Iterations whose active set is at most 4096 regions run their
+    bookkeeping as one workgroup (small_step_kernel); per-phase timing
+    (option timing = 2) forces the four separate kernels everywhere.  Both give
+    the same run bit for bit, including the stops decided inside the fused
+    kernel (capacity, iteration limit, non-finite values, precision limit)."""
+    c1 = W.config1()
+    args = {
+        "d3_deep": (c1["family"], c1["params"], c1["lo"], c1["hi"], 1e-9, 1 << 22, 3),
+        "d8_gauss": (4, W.family_params(4, 8, seed=812), *W.unit_box(8), 1e-5, 1 << 22, 8),
+        "d5_cap": (4, np.array([25.0] * 5 + [0.5] * 5), *W.unit_box(5), 1e-12, 3000, 4),
+        "d3_max_iters": (4, np.array([25.0] * 3 + [0.5] * 3), *W.unit_box(3), 1e-12, 1 << 20, 3),
+        "nonfinite": (3, np.array([-1.0, -1.0, 0.0, 0.0]), *W.unit_box(2), 1e-6, 1 << 20, 4),
+        "precision": (4, np.array([0.1] * 3 + [0.5] * 3), *W.unit_box(3), 0.0, 1 << 20, 4),
+        "grad_d4": (1, W.family_params(1, 4, seed=404), *W.unit_box(4), 1e-8, 1 << 22, 4),
+    }[case]
+    kw = {"max_iters": 7} if case == "d3_max_iters" else {}
+    if case == "precision":
+        kw["abs_tol"] = 1e-300
+    if case == "grad_d4":
+        kw["grad"] = True
+    print(f"case {case}", flush=True)
+    a, act_a, sa = _run_with_timing(0, *args, **kw)
+    b, act_b, sb = _run_with_timing(2, *args, **kw)
+    # (the non-finite case stops in its first iteration, inside the fused kernel)
+    assert sa["iterations"] >= (1 if case == "nonfinite" else 3)
+    for k in ("iterations", "regions_evaluated", "final_active"):
+        assert sa[k] == sb[k], (k, sa[k], sb[k])
+    assert a[-1] == b[-1]
+    for x, y in zip(a[:-1], b[:-1]):
+        np.testing.assert_array_equal(np.asarray(x, dtype=np.float64),
+                                      np.asarray(y, dtype=np.float64))
+    if act_a is not None:
+        for k in ("c", "h", "lvl", "Q", "err", "axis"):
+            np.testing.assert_array_equal(act_a[k], act_b[k])
