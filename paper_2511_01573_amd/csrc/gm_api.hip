@@ -404,9 +404,9 @@ struct ScatterArgs {
 // load of a region is issued before its stores.  scatter_tiles takes the
 // visits tile0, tile0 + tstride, ... of its tile order (the body of
 // scatter_kernel and of the fused small-iteration kernel).
-template <int D>
-__device__ __forceinline__ void scatter_tiles(const ScatterArgs& A, int64_t tile0,
-                                              int64_t tstride) {
+template <int D, bool SPLIT>
+__device__ __forceinline__ void scatter_tiles_t(const ScatterArgs& A, int64_t tile0,
+                                                int64_t tstride) {
   const Status* st = A.st;
   const int64_t n = st->n_prev;
   const int out = st->buf, in = 1 - out;
@@ -425,7 +425,7 @@ __device__ __forceinline__ void scatter_tiles(const ScatterArgs& A, int64_t tile
   // XCD (workgroups go round-robin over the eight), so the parent records that
   // the first tile reads are still in that XCD's L2 for the second.  Visits
   // past either half's end do nothing.
-  const bool paired = R.split != 0;
+  const bool paired = SPLIT;
   const int64_t m = paired ? (R.npar + kTile - 1) / kTile : nt;
   const int64_t nv = paired ? 16 * ((m + 7) / 8) : nt;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -437,61 +437,129 @@ __device__ __forceinline__ void scatter_tiles(const ScatterArgs& A, int64_t tile
       tile = (u & 1) ? m + i : i;
       if ((u & 1) ? tile >= nt : i >= m) continue;  // uniform over the block
     }
-    // Counts of every (row, wavefront) first, one barrier per tile.
-    bool keepv[kTile / kTileThreads];
-    uint64_t masks[kTile / kTileThreads];
+    // The flags of the tile's rows and its offset are loaded together (one
+    // memory round trip), then the counts of every (row, wavefront), one
+    // barrier per tile.
+    constexpr int kRows = kTile / kTileThreads;
+    uint8_t fl[kRows];
 #pragma unroll
-    for (int k = 0; k < kTile / kTileThreads; ++k) {
+    for (int k = 0; k < kRows; ++k) {
       const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
-      keepv[k] = (r < n) && (A.FLAG[r] == 0);
+      fl[k] = A.FLAG[r < n ? r : n - 1];
+    }
+    const int64_t tile_base = A.TOFF[tile];
+    bool keepv[kRows];
+    uint64_t masks[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
+      keepv[k] = (r < n) && (fl[k] == 0);
       masks[k] = __ballot(keepv[k]);
       if (lane == 0) wc[k][w] = __popcll(masks[k]);
     }
     __syncthreads();
-    int64_t base = A.TOFF[tile];
+    // Destination of each row's region: rank p among the kept (parent
+    // record), else its slot in the leaf store (gradient mode); -1 = none.
+    // (p < cap / 2 holds by the scan's capacity check; the tests keep every
+    // store inside its buffer whatever the offsets hold.)
+    int64_t dst[kRows];
+    {
+      int64_t base = tile_base;
 #pragma unroll
-    for (int k = 0; k < kTile / kTileThreads; ++k) {
-      const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
-      int64_t off = base;
-      int64_t rowtot = 0;
+      for (int k = 0; k < kRows; ++k) {
+        const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
+        int64_t off = base, rowtot = 0;
 #pragma unroll
-      for (int i = 0; i < kTileThreads / 64; ++i) {
-        if (i < w) off += wc[k][i];
-        rowtot += wc[k][i];
+        for (int i = 0; i < kTileThreads / 64; ++i) {
+          if (i < w) off += wc[k][i];
+          rowtot += wc[k][i];
+        }
+        const int64_t before = off + __popcll(masks[k] & ((1ull << lane) - 1ull));
+        if (keepv[k]) {
+          dst[k] = (before >= 0 && before < cap) ? before : -1;
+        } else {
+          const int64_t slot = leaf_base + (r - before);
+          dst[k] = (A.LC != nullptr && r < n && slot >= 0 && slot < A.leaf_cap) ? slot : -1;
+        }
+        base += rowtot;
       }
-      const int64_t before = off + __popcll(masks[k] & ((1ull << lane) - 1ull));
-      // (p < cap / 2 holds by the scan's capacity check; the test keeps every
-      // store inside the buffer whatever the offsets hold)
-      if (keepv[k]) {
-        const int64_t p = before;
-        if (p >= 0 && p < cap) {
-          double c[D], h[D];
-          const int lvl = load_region<D>(R, r, c, h);
+    }
+    // Records of kBatch rows are loaded before any of them is stored, so a
+    // wavefront has that many rows' reads in flight at once.
+    constexpr int kBatch = D <= 8 ? 4 : D <= 12 ? 2 : 1;
+#pragma unroll
+    for (int k0 = 0; k0 < kRows; k0 += kBatch) {
+      // Every lane loads (the index clamped into the set), so no loaded
+      // value is merged across a branch before its use: the waits for a
+      // batch's loads come only at its stores.
+      double gc[kBatch][D], gh[kBatch][D];
+      uint16_t gl[kBatch];
+      uint8_t gp[kBatch], ga[kBatch];
+      bool gplus[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int64_t r0 = tile * kTile + (k0 + b) * kTileThreads + threadIdx.x;
+        const int64_t r = r0 < n ? r0 : n - 1;
+        gplus[b] = SPLIT && r >= R.npar;
+        const int64_t q = gplus[b] ? r - R.npar : r;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          gc[b][j] = R.C[j * cap + q];
+          gh[b][j] = R.H[j * cap + q];
+        }
+        gl[b] = R.L[q];
+        gp[b] = SPLIT ? R.PAX[q] : 0;
+        ga[b] = A.AXIS[r];
+      }
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        const int k = k0 + b;
+        const int64_t p = dst[k];
+        if (p < 0) continue;
+        // the child: the parent's split axis halved, the centre moved
+        double c[D], h[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          c[j] = gc[b][j];
+          h[j] = gh[b][j];
+          if (SPLIT && j == gp[b]) {
+            const double hp = gh[b][j] * 0.5;
+            c[j] = gplus[b] ? gc[b][j] + hp : gc[b][j] - hp;
+            h[j] = hp;
+          }
+        }
+        const int lvl = SPLIT ? gl[b] + 1 : gl[b];
+        if (keepv[k]) {
 #pragma unroll
           for (int j = 0; j < D; ++j) {
             Co[j * cap + p] = c[j];
             Ho[j * cap + p] = h[j];
           }
           Lo[p] = (uint16_t)lvl;
-          Po[p] = A.AXIS[r] & kAxisMask;
-        }
-      } else if (A.LC != nullptr && r < n) {
-        const int64_t slot = leaf_base + (r - before);
-        if (slot >= 0 && slot < A.leaf_cap) {
-          double c[D], h[D];
-          const int lvl = load_region<D>(R, r, c, h);
+          Po[p] = ga[b] & kAxisMask;
+        } else {
 #pragma unroll
           for (int j = 0; j < D; ++j) {
-            A.LC[j * A.leaf_cap + slot] = c[j];
-            A.LH[j * A.leaf_cap + slot] = h[j];
+            A.LC[j * A.leaf_cap + p] = c[j];
+            A.LH[j * A.leaf_cap + p] = h[j];
           }
-          A.LL[slot] = (uint16_t)lvl;
+          A.LL[p] = (uint16_t)lvl;
         }
       }
-      base += rowtot;
     }
     __syncthreads();
   }
+}
+
+// (SPLIT: the input set is stored as parent records, as after every
+// iteration but the first.)
+template <int D>
+__device__ __forceinline__ void scatter_tiles(const ScatterArgs& A, int64_t tile0,
+                                              int64_t tstride) {
+  if (A.st->split_in)
+    scatter_tiles_t<D, true>(A, tile0, tstride);
+  else
+    scatter_tiles_t<D, false>(A, tile0, tstride);
 }
 
 template <int D>
