@@ -80,6 +80,46 @@ def build(force: bool = True, jobs: int | None = None) -> str:
     return LIB
 
 
+# Host-sanitizer check program (tests/libgm_sanitize_main.cpp): the library's
+# host-logic units recompiled with AddressSanitizer and UndefinedBehaviorSanitizer
+# on their host side only (device code as in libgm.so), linked with the kernel
+# objects of build() into one executable.
+SAN_UNITS = ("gm_api", "gm_batch", "gm_grad")
+SAN_BUILD = os.path.join(PKG, "_build_san")
+SAN_EXE = os.path.join(PKG, "gm_host_sanitize")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-g"]
+
+
+def build_host_sanitize(jobs: int | None = None) -> str:
+    """Build the host-sanitizer check program (needs the objects of build())."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    units = []
+    for name in SAN_UNITS:
+        units.append((os.path.join(CSRC, name + ".hip"), os.path.join(SAN_BUILD, name + ".o"), SAN_FLAGS))
+    units.append((os.path.join(ROOT, "tests", "libgm_sanitize_main.cpp"),
+                  os.path.join(SAN_BUILD, "libgm_sanitize_main.o"), SAN_FLAGS))
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda u: _compile(u, True), units))
+    errors = [e for _, e in results if e]
+    if errors:
+        raise RuntimeError("\n\n".join(errors))
+    kernels = [o for _, o, _ in _units()
+               if os.path.splitext(os.path.basename(o))[0] not in SAN_UNITS]
+    missing = [o for o in kernels if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"build() first: missing {missing[:3]}")
+    tmp = SAN_EXE + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}"] + SAN_FLAGS + ["-o", tmp] + [o for o, _ in results] + kernels
+    subprocess.run(cmd, check=True)
+    shutil.move(tmp, SAN_EXE)
+    return SAN_EXE
+
+
 if __name__ == "__main__":
     force = "--incremental" not in sys.argv
     print(build(force=force))
+    if "--host-sanitize" in sys.argv:
+        print(build_host_sanitize())
