@@ -62,22 +62,53 @@ def _compile(unit, force):
     return obj, None
 
 
-def build(force: bool = True, jobs: int | None = None) -> str:
-    """Compile every HIP translation unit for gfx950 and link libgm.so."""
-    os.makedirs(BUILD, exist_ok=True)
-    units = _units()
+def _link(objs, lib):
+    tmp = lib + ".tmp"
+    subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs,
+                   check=True)
+    shutil.move(tmp, lib)
+    return lib
+
+
+def _compile_all(units, force, jobs):
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(lambda u: _compile(u, force), units))
     errors = [e for _, e in results if e]
     if errors:
         raise RuntimeError("\n\n".join(errors))
-    objs = [o for o, _ in results]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
-    subprocess.run(cmd, check=True)
-    shutil.move(tmp, LIB)
+    return [o for o, _ in results]
+
+
+def build(force: bool = True, jobs: int | None = None, check: bool = False) -> str:
+    """Compile every HIP translation unit for gfx950 and link libgm.so; with
+    check=True also the -DGM_CHECK build libgm_check.so (one compile pool)."""
+    os.makedirs(BUILD, exist_ok=True)
+    units = _units()
+    cunits = _check_units() if check else []
+    objs = _compile_all(units + cunits, force, jobs)
+    _link(objs[:len(units)], LIB)
+    if check:
+        _link(objs[len(units):], CHECK_LIB)
     return LIB
+
+
+# Bounds-check build: every unit compiled with -DGM_CHECK (kernel index checks
+# that count violations, gm_common.hpp GM_INB) into libgm_check.so, loaded by
+# the bounds-check test in place of libgm.so.
+CHECK_BUILD = os.path.join(PKG, "_build_check")
+CHECK_LIB = os.path.join(PKG, "libgm_check.so")
+
+
+def _check_units():
+    os.makedirs(CHECK_BUILD, exist_ok=True)
+    return [(src, os.path.join(CHECK_BUILD, os.path.basename(obj)), extra + ["-DGM_CHECK"])
+            for src, obj, extra in _units()]
+
+
+def build_check(force: bool = True, jobs: int | None = None) -> str:
+    """Compile every unit with -DGM_CHECK and link libgm_check.so."""
+    return _link(_compile_all(_check_units(), force, jobs), CHECK_LIB)
 
 
 # Host-sanitizer check program (tests/libgm_sanitize_main.cpp): the library's
@@ -100,19 +131,14 @@ def build_host_sanitize(jobs: int | None = None) -> str:
         units.append((os.path.join(CSRC, name + ".hip"), os.path.join(SAN_BUILD, name + ".o"), SAN_FLAGS))
     units.append((os.path.join(ROOT, "tests", "libgm_sanitize_main.cpp"),
                   os.path.join(SAN_BUILD, "libgm_sanitize_main.o"), SAN_FLAGS))
-    jobs = jobs or min(8, os.cpu_count() or 4)
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(lambda u: _compile(u, True), units))
-    errors = [e for _, e in results if e]
-    if errors:
-        raise RuntimeError("\n\n".join(errors))
+    san_objs = _compile_all(units, True, jobs)
     kernels = [o for _, o, _ in _units()
                if os.path.splitext(os.path.basename(o))[0] not in SAN_UNITS]
     missing = [o for o in kernels if not os.path.exists(o)]
     if missing:
         raise RuntimeError(f"build() first: missing {missing[:3]}")
     tmp = SAN_EXE + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}"] + SAN_FLAGS + ["-o", tmp] + [o for o, _ in results] + kernels
+    cmd = [HIPCC, f"--offload-arch={ARCH}"] + SAN_FLAGS + ["-o", tmp] + san_objs + kernels
     subprocess.run(cmd, check=True)
     shutil.move(tmp, SAN_EXE)
     return SAN_EXE
@@ -120,6 +146,6 @@ def build_host_sanitize(jobs: int | None = None) -> str:
 
 if __name__ == "__main__":
     force = "--incremental" not in sys.argv
-    print(build(force=force))
+    print(build(force=force, check="--check" in sys.argv))
     if "--host-sanitize" in sys.argv:
         print(build_host_sanitize())

@@ -816,4 +816,6 @@ AdjFn GM_CAT(adjoint_kernel_f, GM_FAMILY)(int d, bool r9, int part) {
   }
 }
 
+GM_CHECK_UNIT_F(adjoint, GM_FAMILY)
+
 }  // namespace gm

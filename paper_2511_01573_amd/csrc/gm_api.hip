@@ -59,6 +59,7 @@ __global__ void init_kernel(InitArgs A) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t mask = ((int64_t)1 << A.m) - 1;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < A.n0; t += stride) {
+    if (!GM_INB(t, A.cap)) continue;
     for (int j = 0; j < A.d; ++j) {
       const int64_t kj = (t >> (A.m * j)) & mask;
       const double hj = ldexp(A.half[j], -A.m);
@@ -200,7 +201,7 @@ __device__ __forceinline__ void classify_tiles(const ClassifyArgs& A, int64_t ti
 #pragma unroll
     for (int k = 0; k < kTile / kTileThreads; ++k) {
       const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
-      if (r < n) {
+      if (r < n && GM_INB(r, st->cap)) {
         const double err = A.ERR[r];
         const int lvl = split ? L[r >= npar ? r - npar : r] + 1 : L[r];
         bool fin = (err <= ldexp(T, -lvl)) || (aI + err == aI) || (A.AXIS[r] & 0x80);
@@ -225,7 +226,7 @@ __device__ __forceinline__ void classify_tiles(const ClassifyArgs& A, int64_t ti
       se[w] = e;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && GM_INB(tile, (st->cap + kTile - 1) / kTile + 1)) {
       int64_t kk = sk[0];
       dd tq = sq[0], te = se[0];
       for (int i = 1; i < kTileThreads / 64; ++i) {
@@ -274,7 +275,8 @@ __device__ __forceinline__ void scan_body(Status* st, const int64_t* TK, int64_t
   const int64_t nt = (n + kTile - 1) / kTile;
   const int64_t per = (nt + nthr - 1) / nthr;
   const int64_t t0 = (int64_t)threadIdx.x * per;
-  const int64_t t1 = t0 + per < nt ? t0 + per : nt;
+  int64_t t1 = t0 + per < nt ? t0 + per : nt;
+  if (t1 > t0 && !GM_INB(t1 - 1, (st->cap + kTile - 1) / kTile + 1)) t1 = t0;
   int64_t sum = 0;
   dd q = {0.0, 0.0}, e = {0.0, 0.0};
   for (int64_t t = t0; t < t1; ++t) {
@@ -447,7 +449,7 @@ __device__ __forceinline__ void scatter_tiles_t(const ScatterArgs& A, int64_t ti
       const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
       fl[k] = A.FLAG[r < n ? r : n - 1];
     }
-    const int64_t tile_base = A.TOFF[tile];
+    const int64_t tile_base = GM_INB(tile, (cap + kTile - 1) / kTile + 1) ? A.TOFF[tile] : 0;
     bool keepv[kRows];
     uint64_t masks[kRows];
 #pragma unroll
@@ -460,7 +462,7 @@ __device__ __forceinline__ void scatter_tiles_t(const ScatterArgs& A, int64_t ti
     __syncthreads();
     // Destination of each row's region: rank p among the kept (parent
     // record), else its slot in the leaf store (gradient mode); -1 = none.
-    // (p < cap / 2 holds by the scan's capacity check; the tests keep every
+    // (p < cap / 2 holds by the scan's capacity check; the guards keep every
     // store inside its buffer whatever the offsets hold.)
     int64_t dst[kRows];
     {
@@ -476,10 +478,10 @@ __device__ __forceinline__ void scatter_tiles_t(const ScatterArgs& A, int64_t ti
         }
         const int64_t before = off + __popcll(masks[k] & ((1ull << lane) - 1ull));
         if (keepv[k]) {
-          dst[k] = (before >= 0 && before < cap) ? before : -1;
+          dst[k] = GM_GUARD(before, cap) ? before : -1;
         } else {
           const int64_t slot = leaf_base + (r - before);
-          dst[k] = (A.LC != nullptr && r < n && slot >= 0 && slot < A.leaf_cap) ? slot : -1;
+          dst[k] = (A.LC != nullptr && r < n && GM_GUARD(slot, A.leaf_cap)) ? slot : -1;
         }
         base += rowtot;
       }
@@ -501,7 +503,8 @@ __device__ __forceinline__ void scatter_tiles_t(const ScatterArgs& A, int64_t ti
         const int64_t r0 = tile * kTile + (k0 + b) * kTileThreads + threadIdx.x;
         const int64_t r = r0 < n ? r0 : n - 1;
         gplus[b] = SPLIT && r >= R.npar;
-        const int64_t q = gplus[b] ? r - R.npar : r;
+        int64_t q = gplus[b] ? r - R.npar : r;
+        if (!GM_INB(q, cap)) q = 0;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           gc[b][j] = R.C[j * cap + q];
@@ -687,6 +690,50 @@ std::mutex& api_mutex() {
 }
 
 int record_hip_error(hipError_t e) { return hip_fail(e); }
+
+GM_CHECK_UNIT(api)
+
+#ifdef GM_CHECK
+// Self-test of the check path: one index one past its bound, checked and not
+// used (no memory is accessed).
+__global__ void check_selftest_kernel(int64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) (void)GM_INB(n, n);
+}
+
+int check_bounds(int rc) {
+  using PollFn = int (*)(CheckRec*);
+#define GM_POLL_F(name)                                                               \
+  {#name " f1", gm_check_poll_##name##_f1}, {#name " f2", gm_check_poll_##name##_f2}, \
+  {#name " f3", gm_check_poll_##name##_f3}, {#name " f4", gm_check_poll_##name##_f4}, \
+  {#name " f5", gm_check_poll_##name##_f5}, {#name " f6", gm_check_poll_##name##_f6}, \
+  {#name " f7", gm_check_poll_##name##_f7}
+  static const struct {
+    const char* name;
+    PollFn fn;
+  } units[] = {{"api", gm_check_poll_api}, {"batch", gm_check_poll_batch},
+               {"grad", gm_check_poll_grad}, GM_POLL_F(rule), GM_POLL_F(rule9),
+               GM_POLL_F(adjoint), GM_POLL_F(gk)};
+#undef GM_POLL_F
+  std::string first;
+  unsigned long long total = 0;
+  for (const auto& u : units) {
+    CheckRec r = {};
+    if (u.fn(&r) != 0) return hip_fail(hipGetLastError());
+    if (r.count != 0 && first.empty()) {
+      char buf[256];
+      std::snprintf(buf, sizeof buf, "bounds check failed in unit %s, line %d: index %lld, bound %lld",
+                    u.name, r.line, r.index, r.bound);
+      first = buf;
+    }
+    total += r.count;
+  }
+  if (total == 0) return rc;
+  g_hip_err = first + " (" + std::to_string(total) + " violations)";
+  return GM_EHIP;
+}
+#else
+int check_bounds(int rc) { return rc; }
+#endif
 
 void stats_reset() { std::memset(&g_stats, 0, sizeof g_stats); }
 gm_stats& stats_ref() { return g_stats; }
@@ -1327,8 +1374,8 @@ int gm_integrate(int integrand_id, const double* params, int d, const double* lo
   if (!out_est || !out_err) return GM_EINVAL;
   std::lock_guard<std::mutex> lk(api_mutex());
   RunResult rr;
-  rc = run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions,
-                    (hipStream_t)stream, false, &rr);
+  rc = check_bounds(run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions,
+                                 (hipStream_t)stream, false, &rr));
   if (rc != GM_OK) return rc;
   *out_est = rr.I;
   *out_err = rr.E;
@@ -1347,8 +1394,8 @@ int gm_integrate_noalloc(int integrand_id, const double* params, int d, const do
   rc = noalloc_scratch(&base);
   if (rc != GM_OK) return rc;
   RunResult rr;
-  rc = run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions,
-                    (hipStream_t)stream, false, &rr, base);
+  rc = check_bounds(run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions,
+                                 (hipStream_t)stream, false, &rr, base));
   if (rc != GM_OK) return rc;
   *out_est = rr.I;
   *out_err = rr.E;
@@ -1409,6 +1456,8 @@ int gm_eval_regions(int integrand_id, const double* params, int d, const double*
   GM_HIP(hipMemcpyAsync(out_err, ra.ERR, sizeof(double) * n, hipMemcpyDeviceToHost, s));
   GM_HIP(hipMemcpyAsync(ax.data(), ra.AXIS, n, hipMemcpyDeviceToHost, s));
   GM_HIP(hipStreamSynchronize(s));
+  rc = check_bounds(GM_OK);
+  if (rc != GM_OK) return rc;
   for (int64_t r = 0; r < n; ++r) out_axis[r] = ax[r];
   return GM_OK;
 }
@@ -1507,6 +1556,18 @@ int gm_set_option(const char* key, int64_t value) {
   if (!key) return GM_EINVAL;
   std::lock_guard<std::mutex> lk(api_mutex());
   const std::string k(key);
+#ifdef GM_CHECK
+  // (GM_CHECK builds only) "check_selftest" = n: a kernel checks index n
+  // against bound n without accessing memory; the call returns what the
+  // bounds-check path makes of it (GM_EHIP, the violation in
+  // gm_status_string(GM_EHIP)).
+  if (k == "check_selftest") {
+    hipLaunchKernelGGL(check_selftest_kernel, dim3(1), dim3(64), 0, 0, value);
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipDeviceSynchronize());
+    return check_bounds(GM_OK);
+  }
+#endif
   if (k == "init_log2_regions") {
     if (value < 0 || value > 30) return GM_EINVAL;
     g_opt.init_log2 = (int)value;

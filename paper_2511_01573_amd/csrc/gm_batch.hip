@@ -148,6 +148,7 @@ __global__ void batch_init_kernel(BatchArgs A, const int64_t* item_off0, const i
                                   const double* item_lo, const double* item_half, int64_t n0) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n0; r += stride) {
+    if (!GM_INB(r, A.cap)) continue;
     // item of region r: last item with item_off0[i] <= r
     int lo = 0, hi = A.nitems - 1;
     while (lo < hi) {
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(kChunk) void batch_reduce_kernel(BatchArgs A) {
     const int64_t r = k0 + threadIdx.x;
     dd q = {0.0, 0.0}, e = {0.0, 0.0};
     int nf = 0;
-    if (r < k1) {
+    if (r < k1 && GM_INB(r, A.cap)) {
       q.hi = A.Q[r];
       e.hi = A.ERR[r];
       nf = (A.AXIS[r] & kNonfiniteBit) ? 1 : 0;
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(kChunk) void batch_classify_kernel(BatchArgs A) {
     const double T = S.T, aI = fabs(S.I);
     bool keep = false;
     dd fq = {0.0, 0.0}, fe = {0.0, 0.0};
-    if (r < k1) {
+    if (r < k1 && GM_INB(r, A.cap)) {
       const double err = A.ERR[r];
       const bool fin = (err <= ldexp(T, -(int)Lb[r])) || (aI + err == aI) ||
                        (A.AXIS[r] & kGeoBit);
@@ -471,7 +472,9 @@ __global__ __launch_bounds__(256) void batch_scatter_kernel(BatchArgs A) {
   const int64_t cap = A.cap;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_old; r += stride) {
+    if (!GM_INB(r, cap)) continue;
     const uint32_t it = A.IT[in][r];
+    if (!GM_INB(it, A.nitems)) continue;
     const ItemState& S = A.items[it];
     if (S.done) continue;
     const int32_t p = A.RANK[r];
@@ -479,6 +482,7 @@ __global__ __launch_bounds__(256) void batch_scatter_kernel(BatchArgs A) {
     const int64_t c = S.cbase_prev + (r - S.off_prev) / kChunk;
     const int64_t pk = A.CS[c].koff + p;
     const int64_t p0 = S.off + pk, p1 = S.off + S.nk + pk;
+    if (!GM_INB(p0, cap) || !GM_INB(p1, cap)) continue;
     const int ax = A.AXIS[r] & kAxisMask;
     for (int j = 0; j < S.d; ++j) {
       const double cj = A.C[in][j * cap + r];
@@ -917,6 +921,8 @@ int run_batch(int n, const int* fam, const double* params, const int* d, const d
   return worst;
 }
 
+GM_CHECK_UNIT(batch)
+
 }  // namespace gm
 
 using namespace gm;
@@ -931,8 +937,9 @@ int gm_integrate_batch(int n, const int* integrand_ids, const double* params, co
       !out_err || !out_status || max_regions_total < 1)
     return GM_EINVAL;
   std::lock_guard<std::mutex> lk(api_mutex());
-  return run_batch(n, integrand_ids, params, d, lo, hi, rel_tol, abs_tol, max_regions_total,
-                   out_est, out_err, out_status, (hipStream_t)stream);
+  return check_bounds(run_batch(n, integrand_ids, params, d, lo, hi, rel_tol, abs_tol,
+                               max_regions_total, out_est, out_err, out_status,
+                               (hipStream_t)stream));
 }
 
 int gm_set_tile(int d, int integrand_id, int lanes_per_region, int grid_blocks) {

@@ -14,6 +14,69 @@ namespace gm {
 constexpr int kMaxDim = 16;
 constexpr int kMinDim = 2;
 
+// ---------------------------------------------------------------------------
+// Bounds checks of the -DGM_CHECK build.  GM_INB(i, n) is true when
+// 0 <= i < n.  In a GM_CHECK build a false result also counts a violation and
+// records the first one (source line, index, bound) in this translation
+// unit's device record; the caller skips the access it guards, so the kernel
+// still ends normally, and the host turns a nonzero count into GM_EHIP after
+// the call (gm_check_poll_* of every unit).  Without GM_CHECK the check is the
+// constant true and compiles to nothing; GM_GUARD(i, n) is the same check for
+// accesses that are guarded in every build.
+// ---------------------------------------------------------------------------
+struct CheckRec {
+  unsigned long long count;
+  long long index, bound;
+  int line;
+  int pad;
+};
+
+#ifdef GM_CHECK
+static __device__ CheckRec g_chk;
+
+__device__ __noinline__ inline void check_fail(int64_t i, int64_t n, int line) {
+  if (atomicAdd(&g_chk.count, 1ull) == 0ull) {
+    g_chk.index = i;
+    g_chk.bound = n;
+    g_chk.line = line;
+  }
+}
+
+__device__ __forceinline__ bool in_bounds(int64_t i, int64_t n, int line) {
+  if (i >= 0 && i < n) return true;
+  check_fail(i, n, line);
+  return false;
+}
+#define GM_INB(i, n) ::gm::in_bounds((int64_t)(i), (int64_t)(n), __LINE__)
+
+// Host: copy this unit's record to *out and clear it; 0 or -1 (HIP error).
+#define GM_CHECK_POLL_BODY                                                              \
+  {                                                                                     \
+    const ::gm::CheckRec z = {};                                                        \
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(::gm::g_chk), sizeof *out) != hipSuccess)   \
+      return -1;                                                                        \
+    if (out->count != 0 &&                                                              \
+        hipMemcpyToSymbol(HIP_SYMBOL(::gm::g_chk), &z, sizeof z) != hipSuccess)         \
+      return -1;                                                                        \
+    return 0;                                                                           \
+  }
+#define GM_CAT3_(a, b, c) a##b##c
+#define GM_CAT3(a, b, c) GM_CAT3_(a, b, c)
+// One poll function per translation unit: gm_check_poll_<name>[_f<family>].
+#define GM_CHECK_UNIT(name) \
+  int GM_CAT3(gm_check_poll_, name, )(::gm::CheckRec* out) GM_CHECK_POLL_BODY
+#define GM_CHECK_UNIT_F(name, fam) \
+  int GM_CAT3(gm_check_poll_, name, GM_CAT3(_f, fam, ))(::gm::CheckRec* out) GM_CHECK_POLL_BODY
+#define GM_GUARD(i, n) GM_INB(i, n)
+#else
+#define GM_INB(i, n) true
+#define GM_CHECK_UNIT(name)
+#define GM_CHECK_UNIT_F(name, fam)
+// A guard that stays in every build (the access is skipped when the index
+// is out of range); a GM_CHECK build also counts it as a violation.
+#define GM_GUARD(i, n) ((int64_t)(i) >= 0 && (int64_t)(i) < (int64_t)(n))
+#endif
+
 // Integrand families (the numbering of include/gm.h).
 enum Family : int {
   kOsc = 1,
@@ -162,6 +225,11 @@ __device__ __forceinline__ int load_region(const RegionSrc& R, int64_t r, double
                                            double (&h)[D]) {
   const bool plus = R.split && r >= R.npar;
   const int64_t q = plus ? r - R.npar : r;
+  if (!GM_INB(q, R.cap)) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = h[j] = 0.0;
+    return 0;
+  }
 #pragma unroll
   for (int j = 0; j < D; ++j) {
     c[j] = R.C[j * R.cap + q];

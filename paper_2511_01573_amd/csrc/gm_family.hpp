@@ -156,6 +156,7 @@ struct RegionResult {
 };
 
 __device__ __forceinline__ void store_result(const RuleArgs& A, int64_t r, const RegionResult& o) {
+  if (!GM_INB(r, A.cap)) return;
   A.Q[r] = o.q;
   A.ERR[r] = o.err;
   A.AXIS[r] = (uint8_t)(o.axis | (o.nonfinite ? kNonfiniteBit : 0) | (o.geo ? kGeoBit : 0));

@@ -261,4 +261,6 @@ RuleKernelFn GM_GK_CAT(gk_kernel_f, GM_RULE_FAMILY)(int d, bool batch) {
   }
 }
 
+GM_CHECK_UNIT_F(gk, GM_RULE_FAMILY)
+
 }  // namespace gm

@@ -55,6 +55,8 @@ static AdjFn adj_fn(int d, int fam, bool r9, int part) {
   }
 }
 
+GM_CHECK_UNIT(grad)
+
 }  // namespace gm
 
 using namespace gm;
@@ -71,7 +73,8 @@ extern "C" int gm_integrate_grad(int integrand_id, const double* params, int d, 
   std::lock_guard<std::mutex> lk(api_mutex());
   hipStream_t s = (hipStream_t)stream;
   RunResult rr;
-  rc = run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions, s, true, &rr);
+  rc = check_bounds(
+      run_adaptive(integrand_id, params, d, lo, hi, rel_tol, abs_tol, max_regions, s, true, &rr));
   if (rc != GM_OK) return rc;
   if (rr.status == GM_NONFINITE) {
     *out_est = rr.I;
@@ -131,6 +134,8 @@ extern "C" int gm_integrate_grad(int integrand_id, const double* params, int d, 
     (void)hipFree(part);
     (void)hipFree(dout);
     if (e != hipSuccess) return record_hip_error(e);
+    rc = check_bounds(GM_OK);
+    if (rc != GM_OK) return rc;
   }
   *out_est = rr.I;
   *out_err = rr.E;

@@ -85,6 +85,27 @@ std::mutex& api_mutex();
 // Record a HIP error for gm_status_string(GM_EHIP) and return GM_EHIP.
 int record_hip_error(hipError_t e);
 
+// Bounds checks of a GM_CHECK build (gm_common.hpp): called after a call's
+// device work has finished, polls every translation unit's check record and
+// returns GM_EHIP, with the first violation as gm_status_string(GM_EHIP), if
+// any unit counted one; otherwise (and always without GM_CHECK) returns rc.
+int check_bounds(int rc);
+#ifdef GM_CHECK
+#define GM_DECLARE_POLL_F(name)                                                          \
+  int gm_check_poll_##name##_f1(CheckRec*); int gm_check_poll_##name##_f2(CheckRec*);    \
+  int gm_check_poll_##name##_f3(CheckRec*); int gm_check_poll_##name##_f4(CheckRec*);    \
+  int gm_check_poll_##name##_f5(CheckRec*); int gm_check_poll_##name##_f6(CheckRec*);    \
+  int gm_check_poll_##name##_f7(CheckRec*);
+int gm_check_poll_api(CheckRec*);
+int gm_check_poll_batch(CheckRec*);
+int gm_check_poll_grad(CheckRec*);
+GM_DECLARE_POLL_F(rule)
+GM_DECLARE_POLL_F(rule9)
+GM_DECLARE_POLL_F(adjoint)
+GM_DECLARE_POLL_F(gk)
+#undef GM_DECLARE_POLL_F
+#endif
+
 // The retired-leaf store of the last gradient-mode forward run (SoA).
 struct LeafView {
   const double* C;

@@ -433,4 +433,6 @@ RuleKernelFn GM_CAT(rule_kernel_f, GM_RULE_FAMILY)(int d, int log2l, bool batch)
   return batch ? rule_fn<true>(d, log2l) : rule_fn<false>(d, log2l);
 }
 
+GM_CHECK_UNIT_F(rule, GM_RULE_FAMILY)
+
 }  // namespace gm

@@ -345,4 +345,6 @@ RuleKernelFn GM_R9_CAT(rule9_kernel_f, GM_RULE_FAMILY)(int d, bool batch, bool w
   }
 }
 
+GM_CHECK_UNIT_F(rule9, GM_RULE_FAMILY)
+
 }  // namespace gm
