@@ -225,6 +225,10 @@ size_t gm_workspace_bytes(int d, int64_t max_regions, int mode);
  *                        (I, E).  gm_integrate / gm_integrate_grad only
  *                        (gm_integrate_batch returns GM_EINVAL).  Default 0.
  *   "log"                1 = print one line per iteration to stderr (default 0)
+ *   "check_selftest"     bounds-check builds (-DGM_CHECK) only: a kernel checks
+ *                        index n = value against bound n without accessing
+ *                        memory; returns GM_EHIP with the violation as
+ *                        gm_status_string(GM_EHIP) (GM_EINVAL in normal builds)
  */
 int gm_set_option(const char* key, int64_t value);
 
