@@ -48,7 +48,7 @@ HBM_PEAK_GBPS = 8000.0
 # per-coordinate terms, the outer function (exp / cos / reciprocal / powers)
 # and the compensated accumulation.  Cross-checked against the
 # SQ_INSTS_VALU_*_F64 counters (profiles/).
-FLOPS_PER_EVAL = {1: 42.75, 2: 7.0, 3: 17.75, 4: 32.5, 5: 32.75, 6: 32.5, 7: 8.5}
+FLOPS_PER_EVAL = {1: 42.75, 2: 7.0, 3: 16.8125, 4: 32.5, 5: 32.75, 6: 32.5, 7: 8.5}
 
 # HBM traffic of the rule kernel, per launch, measured with rocprofv3 --pmc
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a

@@ -13,15 +13,16 @@ namespace gm {
 // Corner sweep: binary tree over coordinates D-U .. D-1 below a prefix.
 // ---------------------------------------------------------------------------
 // Arguments of the 2^M corners below prefix s over coordinates J .. J+M-1, in
-// the tree's order (sign + before sign -).
+// the tree's order (sign + before sign -); a chain that starts here (no
+// prefix) starts with the family's corner bias.
 template <int D, int FAM, int J, int M, bool HAS_PREFIX>
 __device__ __forceinline__ void leaf_args(double s, const double (&t5p)[D], const double (&t5m)[D],
                                           double* out) {
   if constexpr (M == 0) {
     out[0] = s;
   } else {
-    const double a = HAS_PREFIX ? Fam<FAM>::comb(s, t5p[J]) : t5p[J];
-    const double b = HAS_PREFIX ? Fam<FAM>::comb(s, t5m[J]) : t5m[J];
+    const double a = HAS_PREFIX ? Fam<FAM>::comb(s, t5p[J]) : Fam<FAM>::corner_first(t5p[J]);
+    const double b = HAS_PREFIX ? Fam<FAM>::comb(s, t5m[J]) : Fam<FAM>::corner_first(t5m[J]);
     leaf_args<D, FAM, J + 1, M - 1, true>(a, t5p, t5m, out);
     leaf_args<D, FAM, J + 1, M - 1, true>(b, t5p, t5m, out + (1 << (M - 1)));
   }
@@ -39,16 +40,14 @@ __device__ __forceinline__ void corner_tree(const DevParams& P, double s, const 
                                             const double (&t5m)[D], double& local) {
   constexpr int LW = U < kLeafLog2 ? U : kLeafLog2;
   if constexpr (K == U - LW) {
-    double a[1 << LW], f[1 << LW];
+    double a[1 << LW];
     leaf_args<D, FAM, D - U + K, LW, HAS_PREFIX>(s, t5p, t5m, a);
-    Fam<FAM>::template outer_n<D, (1 << LW)>(P, a, f);
-#pragma unroll
-    for (int i = 0; i < (1 << LW); ++i) local += f[i];
+    Fam<FAM>::template accumulate_n<D, (1 << LW)>(P, a, local);
   } else {
     constexpr int j = D - U + K;
     if constexpr (!HAS_PREFIX && K == 0) {
-      corner_tree<D, FAM, U, K + 1, true>(P, t5p[j], t5p, t5m, local);
-      corner_tree<D, FAM, U, K + 1, true>(P, t5m[j], t5p, t5m, local);
+      corner_tree<D, FAM, U, K + 1, true>(P, Fam<FAM>::corner_first(t5p[j]), t5p, t5m, local);
+      corner_tree<D, FAM, U, K + 1, true>(P, Fam<FAM>::corner_first(t5m[j]), t5p, t5m, local);
     } else {
       corner_tree<D, FAM, U, K + 1, true>(P, Fam<FAM>::comb(s, t5p[j]), t5p, t5m, local);
       corner_tree<D, FAM, U, K + 1, true>(P, Fam<FAM>::comb(s, t5m[j]), t5p, t5m, local);
@@ -68,7 +67,7 @@ __device__ __forceinline__ void corner_sweep(const DevParams& P, const double (&
 #pragma unroll
   for (int j = 0; j < LB; ++j) {
     const double t = ((lane_bits >> j) & 1u) ? t5m[j] : t5p[j];
-    pl = (j == 0) ? t : Fam<FAM>::comb(pl, t);
+    pl = (j == 0) ? Fam<FAM>::corner_first(t) : Fam<FAM>::comb(pl, t);
   }
   for (uint32_t m = 0; m < (1u << NOUT); ++m) {
     double pre = pl;
@@ -78,7 +77,7 @@ __device__ __forceinline__ void corner_sweep(const DevParams& P, const double (&
       (void)dummy;
       const int j = LB + q;
       const double t = ((m >> q) & 1u) ? t5m[j] : t5p[j];
-      pre = (LB == 0 && q == 0) ? t : Fam<FAM>::comb(pre, t);
+      pre = (LB == 0 && q == 0) ? Fam<FAM>::corner_first(t) : Fam<FAM>::comb(pre, t);
     }
     double local = 0.0;
     corner_tree<D, FAM, U, 0, (LB + NOUT) != 0>(P, pre, t5p, t5m, local);

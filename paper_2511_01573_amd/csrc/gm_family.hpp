@@ -68,7 +68,10 @@ struct Fam {
   // (1 + s)^-(d+1) needs (1 + s)^(d+1): binary powering
   template <int D>
   __device__ static __forceinline__ double cpk_power(double s) {
-    const double b = 1.0 + s;
+    return cpk_power_of_base<D>(1.0 + s);
+  }
+  template <int D>
+  __device__ static __forceinline__ double cpk_power_of_base(double b) {
     double y = 1.0, p = b;
     int e = D + 1;
     bool first = true;
@@ -113,6 +116,34 @@ struct Fam {
         const double s8 = s4 * s4;
         f[i] = (s8 * s2) * s[i];
       }
+    }
+  }
+  // Constant the corner sweep folds into the first term of each corner
+  // argument (once per subtree instead of once per corner): the corner peak's
+  // 1 of 1 + sum a_j x_j.
+  static constexpr bool kCornerBias = (FAM == kCornerPeak);
+  __device__ static __forceinline__ double corner_first(double t) {
+    if constexpr (kCornerBias) return 1.0 + t;
+    else return t;
+  }
+  // local + G(s[0]) + ... + G(s[N-1]), added in that order (the corner sweep's
+  // sum; s[i] carries the corner bias, so the corner peak's base 1 + sum a_j x_j
+  // arrives formed).
+  template <int D, int N>
+  __device__ static __forceinline__ void accumulate_n(const DevParams& P, const double (&s)[N],
+                                                     double& local) {
+    if constexpr (FAM == kCornerPeak) {
+      double a[N], f[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) a[i] = cpk_power_of_base<D>(s[i]);
+      fm::rcp_n<N>(a, f);
+#pragma unroll
+      for (int i = 0; i < N; ++i) local += f[i];
+    } else {
+      double f[N];
+      outer_n<D, N>(P, s, f);
+#pragma unroll
+      for (int i = 0; i < N; ++i) local += f[i];
     }
   }
   template <int D>
