@@ -187,8 +187,13 @@ void rule_tpr_kernel(RuleArgs A) {
   const int64_t stride = (int64_t)gridDim.x * kRuleBlock;
   dd qs = {0.0, 0.0}, es = {0.0, 0.0};
   int nonfin = 0;
-  int64_t r = start + (int64_t)blockIdx.x * kRuleBlock + threadIdx.x;
-  for (; r < end; r += stride) {
+  // A split set holds the two children of parent q at q and q + n_par; lane
+  // v takes child v & 1 of parent v >> 1, so siblings sit in neighbouring
+  // lanes and a wavefront reads each parent record once.
+  const bool pairs = R.split && end == 2 * R.npar;
+  int64_t v = start + (int64_t)blockIdx.x * kRuleBlock + threadIdx.x;
+  for (; v < end; v += stride) {
+    const int64_t r = pairs ? ((v & 1) ? R.npar + (v >> 1) : (v >> 1)) : v;
     double c[D], h[D];
     const int lvl = load_region<D>(R, r, c, h);
     double volo;
