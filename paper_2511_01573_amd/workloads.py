@@ -18,7 +18,7 @@ NAMES = {1: "oscillatory", 2: "product_peak", 3: "corner_peak", 4: "gaussian", 5
 
 # Sum of a_j per family at d = 8 ("difficulty").  Calibrated once on the CPU
 # oracle so that rel_tol = 1e-5 needs between 1e4 and 1e6 evaluated regions,
-# then frozen (input recipe).
+# then frozen.
 DIFFICULTY_D8 = {OSCILLATORY: 9.0, PRODUCT_PEAK: 15.0, CORNER_PEAK: 2.0, GAUSSIAN: 13.0,
                  C0: 4.0, DISCONTINUOUS: 10.0}
 # Batch difficulty: sum(a) = BATCH_SCALE * b_family * d / 8.  At 0.35 each of
