@@ -17,7 +17,9 @@ then the compact headline as the LAST line (well under 4 KB), holding
   split_compaction  classify + scan + scatter against the HBM peak;
   cpu_baseline      the CPU oracle on a bounded sample of the workload;
   batch, grad, ...  one-number summaries of the modes against
-                    one-call-per-integral.
+                    one-call-per-integral;
+and the time to tolerance per rel_tol: the sum over its six integrals of
+each call's median over the timed steps (default 5, after 1 warm-up step).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--detail-out F]
 """
@@ -64,7 +66,7 @@ RULE_SOURCES = [os.path.join(ROOT, "paper_2511_01573_amd", "csrc", f)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true", help="skip batch/grad comparisons")
@@ -663,6 +665,11 @@ def main():
     d = 8
     alg_bytes = regions / launches * (8 * d + 1 + 17)
     last = steps[-1]
+    # time to tolerance of each integral: the median of its timed calls (the
+    # warm-up calls load the code objects and size the workspace)
+    for i, r in enumerate(last):
+        r["seconds"] = float(np.median([st[i]["seconds"] for st in steps]))
+        r["timed_calls"] = len(steps)
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import closed_forms
     flags = []
@@ -702,8 +709,9 @@ def main():
                      "rule_kernel_s": rule_s, "rule_launches": launches,
                      "rule_avg_launch_ms": rule_s / launches * 1e3,
                      "rule_evals_per_s": evals / rule_s},
-        "cases": [{k: c[k] for k in ("name", "status", "seconds", "evals", "regions", "iterations",
-                                     "I", "E", "rel_err_vs_closed_form")} for c in last],
+        "cases": [{k: c[k] for k in ("name", "status", "seconds", "timed_calls", "evals", "regions",
+                                     "iterations", "I", "E", "rel_err_vs_closed_form")}
+                  for c in last],
         "flags": flags,
     }
     if args.rule == 0:
