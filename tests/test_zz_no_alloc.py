@@ -86,3 +86,35 @@ def test_noalloc_takes_no_device_memory():
     free1, _ = torch.cuda.mem_get_info()
     assert st in (gm.OK, gm.MAX_REGIONS)
     assert free0 - free1 < 1 << 20, (free0, free1, need)
+
+
+@pytest.mark.parametrize("opts", [{"rule": 2, "err_model": 1}, {"rule": 1}, {"prune": 1},
+                                  {"graph_iters": 1}])
+def test_noalloc_matches_gm_integrate_under_options(opts):
+    """The options act on the no-allocation entry point as on gm_integrate:
+    the degree-9 rule with the null-rule error model, the Gauss-Kronrod rule,
+    memory-pressure pruning on a store that overflows, one iteration per
+    status read."""
+    if "rule" in opts and opts["rule"] == 1:
+        fam, d, tau, cap = W.GAUSSIAN, 3, 1e-10, 1 << 14
+    elif "prune" in opts:
+        fam, d, tau, cap = W.GAUSSIAN, 8, 1e-7, 1 << 15
+    else:
+        fam, d, tau, cap = W.OSCILLATORY, 6, 1e-7, 1 << 16
+    p = W.family_params(fam, d, seed=700 + d)
+    assert gm.workspace_bytes(d, cap, 0) <= SCRATCH
+    defaults = {"rule": 0, "err_model": 0, "prune": 0, "graph_iters": 0}
+    for k, v in opts.items():
+        gm.set_option(k, v)
+    try:
+        print(f"case noalloc options {opts}", flush=True)
+        r = gm.integrate_noalloc(fam, p, *W.unit_box(d), tau, 1e-16, cap)
+        s = gm.last_stats()
+        ref = gm.integrate(fam, p, *W.unit_box(d), tau, 1e-16, cap)
+        rs = gm.last_stats()
+    finally:
+        for k in opts:
+            gm.set_option(k, defaults[k])
+    assert r == ref, (r, ref)
+    for key in ("iterations", "regions_evaluated", "max_active", "final_active", "finished"):
+        assert s[key] == rs[key], key
