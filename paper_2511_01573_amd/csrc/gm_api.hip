@@ -198,18 +198,35 @@ __device__ __forceinline__ void classify_tiles(const ClassifyArgs& A, int64_t ti
   for (int64_t tile = tile0; tile < nt; tile += tstride) {
     int64_t keep = 0;
     dd q = {0.0, 0.0}, e = {0.0, 0.0};
+    // Every row's inputs are loaded first, by every lane (index clamped into
+    // the set, Q whether or not it is needed), so the tile costs one memory
+    // round trip instead of two per row (the flag stores would otherwise keep
+    // the next row's loads behind them).
+    constexpr int kRows = kTile / kTileThreads;
+    double errv[kRows], qv[kRows];
+    int lvlv[kRows];
+    uint8_t axv[kRows];
 #pragma unroll
-    for (int k = 0; k < kTile / kTileThreads; ++k) {
+    for (int k = 0; k < kRows; ++k) {
+      const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
+      const int64_t rc = r < n ? r : n - 1;
+      errv[k] = A.ERR[rc];
+      qv[k] = A.Q[rc];
+      axv[k] = A.AXIS[rc];
+      lvlv[k] = L[(split && rc >= npar) ? rc - npar : rc];  // (+ split below)
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
       const int64_t r = tile * kTile + k * kTileThreads + threadIdx.x;
       if (r < n && GM_INB(r, st->cap)) {
-        const double err = A.ERR[r];
-        const int lvl = split ? L[r >= npar ? r - npar : r] + 1 : L[r];
-        bool fin = (err <= ldexp(T, -lvl)) || (aI + err == aI) || (A.AXIS[r] & 0x80);
+        const double err = errv[k];
+        const int lvl = lvlv[k] + (split ? 1 : 0);
+        bool fin = (err <= ldexp(T, -lvl)) || (aI + err == aI) || (axv[k] & 0x80);
         if (SECOND && !fin) fin = err <= ldexp(T, prune_k - lvl);
         if (hist_on && !fin) atomicAdd(&shist[prune_level(err, T, lvl)], 1u);
         A.FLAG[r] = fin ? 1 : 0;
         if (fin) {
-          dd_add(q, A.Q[r]);
+          dd_add(q, qv[k]);
           dd_add(e, err);
         } else {
           keep += 1;
